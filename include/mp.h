@@ -1,0 +1,170 @@
+/*
+ * mp.h -- C ABI of libmp: matrix profile of a time series on one MI355X
+ * (gfx950) GPU, computed with the diagonal-wise incremental distance sweep of
+ * Akbarinia & Cloez, "Efficient Matrix Profile Computation Using Different
+ * Distance Functions" (arXiv 1901.05708).
+ *
+ * Common conventions (every entry point):
+ *
+ *  - Indexing is 0-based. A series T has n samples t_0..t_{n-1}; the window
+ *    T_{i,m} = <t_i .. t_{i+m-1}> exists for 0 <= i < N = n - m + 1
+ *    (Def. 2.2). A pair of windows (i, j) is admissible iff |i - j| >= excl.
+ *  - Outputs: P[i] is the distance from window i to its nearest admissible
+ *    window (Def. 2.4) and I[i] that window's start index. A row with no
+ *    admissible finite candidate gets P[i] = +inf and I[i] = -1 (N <= excl,
+ *    or, z-normalized, a constant window / only constant candidates).
+ *    Every reported P[i] is the distance of the pair (i, I[i]) recomputed
+ *    directly in FP64 from T; when several windows are within the precision
+ *    bound of the minimum any of them may be reported.
+ *  - Pointers T, P, I are DEVICE pointers (hipMalloc or torch CUDA tensors,
+ *    on the current HIP device); T holds n doubles, P holds N doubles, I holds
+ *    N int64. The caller owns them. T is read-only; P and I are written
+ *    entirely. T must be finite with |t| < 1e30 (larger magnitudes could
+ *    meet the sentinel values used for out-of-range pairs).
+ *  - stream is a hipStream_t (NULL = the legacy default stream). Calls are
+ *    stream-ordered and asynchronous: they return after enqueueing the
+ *    kernels, and the caller synchronizes before reading P and I.
+ *  - excl <= 0 selects the default exclusion ceil(m/4); excl = 1 reproduces
+ *    the paper's loops (every window except itself).
+ *  - precision: MP_FP64 runs the whole sweep in double precision.
+ *    MP_FP32_REFRESH runs the bulk of the recurrence in single precision,
+ *    restarted from an exact FP64 value every R rows, with FP64 window
+ *    statistics and FP64 rescoring of every winner; rows it cannot certify
+ *    within MP_FP32_RTOL are recomputed in FP64.
+ *  - R is the refresh interval (rows between exact FP64 restarts of the
+ *    recurrence); R = 0 lets the library choose.
+ *  - Errors: functions return MP_OK (0) or a negative code. Arguments are
+ *    validated before any HIP call; on error nothing is enqueued and P, I are
+ *    left untouched (except MP_EHIP, after which their content is undefined).
+ *    No C++ exception crosses the ABI. mp_strerror() describes the last error
+ *    of the calling thread.
+ *  - Ownership of internal state: the library keeps a grow-only device
+ *    workspace per device, and for mp_batch a cache of captured HIP graphs;
+ *    mp_release() frees both. Calls on one device must not overlap in time
+ *    (they share the workspace); serialize them on one stream.
+ */
+#ifndef MP_H
+#define MP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MP_OK 0
+#define MP_EINVAL (-1)       /* invalid argument                               */
+#define MP_ENOMEM (-2)       /* device allocation failed                       */
+#define MP_EHIP (-3)         /* a HIP runtime call failed (see mp_strerror)    */
+#define MP_EUNSUPPORTED (-4) /* the current device is not a gfx950 GPU         */
+
+#define MP_FP64 0
+#define MP_FP32_REFRESH 1
+
+#define MP_KIND_AAMP 0  /* pure Euclidean                                      */
+#define MP_KIND_PNORM 1 /* p-norm                                              */
+#define MP_KIND_ACAMP 2 /* z-normalized Euclidean                              */
+
+/* Relative tolerance on profile values guaranteed by MP_FP32_REFRESH. */
+#define MP_FP32_RTOL 1e-4
+
+/* Largest supported series length (keys pack a window index in 31 bits). */
+#define MP_MAX_N ((int64_t)1 << 31)
+
+/*
+ * mp_aamp -- pure Euclidean matrix profile (AAMP).
+ * Distance: D_{i,j} = sqrt(sum_{l<m} (t_{i+l} - t_{j+l})^2)   (Def. 2.5, Eq. 1).
+ * Swept with the incremental update of Lemma 1 (Eq. 4) along diagonals,
+ * comparing squared distances and taking one square root per output (Sec. 3.2).
+ * Requires 1 <= m <= n <= MP_MAX_N.
+ */
+int mp_aamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precision,
+            int32_t R, double *P, int64_t *I, void *stream);
+
+/*
+ * mp_pnorm -- p-norm matrix profile (AAMP extended to L^p, Sec. 3.3).
+ * Distance: DP_{i,j} = (sum_{l<m} |t_{i+l} - t_{j+l}|^p)^(1/p)  (Def. 2.6, Eq. 2,
+ * read with an absolute value), real p >= 1; updated with Lemma 2. p = 2 gives
+ * exactly the result of mp_aamp. p must be finite and >= 1.
+ */
+int mp_pnorm(const double *T, int64_t n, int32_t m, double p, int32_t excl,
+             int32_t precision, int32_t R, double *P, int64_t *I, void *stream);
+
+/*
+ * mp_acamp -- z-normalized Euclidean matrix profile (ACAMP, Sec. 4).
+ * Distance: DZ_{i,j} = sqrt(sum_l ((t_{i+l}-mu_i)/s_i - (t_{j+l}-mu_j)/s_j)^2)
+ * (Def. 2.7, Eq. 3) with population standard deviations; equivalently
+ * DZ^2 = 2m(1 - rho_{i,j}) (Lemma 3, Eq. 5). A window whose samples are all
+ * equal has s = 0 and infinite distance to everything (Sec. 1).
+ */
+int mp_acamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precision,
+             int32_t R, double *P, int64_t *I, void *stream);
+
+/*
+ * One series of a batch. Offsets are in elements. Series b occupies
+ * T_cat[t_off .. t_off + n) and its N_b = n - m + 1 outputs go to
+ * P_cat[out_off ..), I_cat[out_off ..); I values are local to the series.
+ * kind is MP_KIND_*; p is used by MP_KIND_PNORM only; excl and R as above.
+ */
+typedef struct mp_job {
+    int64_t t_off;
+    int64_t n;
+    int64_t out_off;
+    int32_t m;
+    int32_t kind;
+    int32_t excl;
+    int32_t R;
+    double p;
+} mp_job;
+
+/*
+ * mp_batch -- matrix profiles of many independent series in one persistent
+ * launch of the sweep. jobs is a HOST array of njobs entries (read during the
+ * call only). The first call with a given job table and precision captures the
+ * whole pipeline into a HIP graph; later calls with an identical table,
+ * precision, pointers and stream replay it. Output ranges of different jobs
+ * must not overlap. Each job obeys the single-series rules above.
+ */
+int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
+             double *P_cat, int64_t *I_cat, void *stream);
+
+/* Human-readable description of an error code, including the HIP error text
+ * of the calling thread's last MP_EHIP. Never NULL; the string is owned by the
+ * library and valid until the next call on the same thread. */
+const char *mp_strerror(int code);
+
+/* Free the device workspace and graph cache of every device. Safe to call at
+ * any time no call is in flight; later calls re-allocate. */
+void mp_release(void);
+
+/*
+ * Profiling. mp_set_profiling(1) clears the accumulated figures and from then
+ * on every call records HIP events on its own stream around each phase; this
+ * adds no host synchronization to the calls. mp_profile_read() waits for the
+ * recorded events and returns the figures summed over all calls made since
+ * profiling was switched on (timings in milliseconds of GPU time), with the
+ * configuration fields of the most recent call. mp_set_profiling(0) stops
+ * recording. Returns MP_OK, or MP_EINVAL if out is NULL.
+ */
+typedef struct mp_stats {
+    double ms_prep;          /* window statistics, difference streams, key fill */
+    double ms_sweep;         /* the diagonal sweep (all its launches)           */
+    double ms_finalize;      /* rescoring, certification and fallback           */
+    int64_t pairs;           /* admissible unordered pairs                      */
+    int64_t fallback_rows;   /* rows recomputed exactly in FP64                 */
+    int32_t calls;           /* calls accumulated                               */
+    int32_t sweep_launches;  /* sweep kernel launches accumulated               */
+    int32_t refresh_rows;    /* R used by the most recent call                  */
+    int32_t diags_per_lane;  /* diagonals per lane of the band kernel, most recent call */
+    int32_t items;           /* work items (diagonal band x row segment), most recent call */
+    int32_t reserved;
+} mp_stats;
+
+void mp_set_profiling(int on);
+int mp_profile_read(mp_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MP_H */

@@ -1,0 +1,213 @@
+"""Python binding of libmp (include/mp.h): matrix profiles on an MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libmp.so. PyTorch supplies device memory and the stream. There is
+no CPU fallback: importing works without a GPU, but every call needs the
+built library and a gfx950 device and raises otherwise.
+
+    import torch, paper_1901_05708_amd as mp
+    T = torch.as_tensor(series, dtype=torch.float64, device="cuda")
+    P, I = mp.aamp(T, m=64)                     # pure Euclidean (AAMP)
+    P, I = mp.pnorm(T, m=128, p=3.0)            # p-norm
+    P, I = mp.acamp(T, m=256, precision="fp32") # z-normalized (ACAMP)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmp.so")
+
+MP_OK, MP_EINVAL, MP_ENOMEM, MP_EHIP, MP_EUNSUPPORTED = 0, -1, -2, -3, -4
+MP_FP64, MP_FP32_REFRESH = 0, 1
+KIND_AAMP, KIND_PNORM, KIND_ACAMP = 0, 1, 2
+FP32_RTOL = 1e-4
+
+EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_strerror", "mp_release",
+            "mp_set_profiling", "mp_profile_read")
+
+
+class MpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libmp error {code}: {msg}")
+        self.code = code
+
+
+class MpJob(ctypes.Structure):
+    _fields_ = [("t_off", ctypes.c_int64), ("n", ctypes.c_int64), ("out_off", ctypes.c_int64),
+                ("m", ctypes.c_int32), ("kind", ctypes.c_int32), ("excl", ctypes.c_int32),
+                ("R", ctypes.c_int32), ("p", ctypes.c_double)]
+
+
+class MpStats(ctypes.Structure):
+    _fields_ = [("ms_prep", ctypes.c_double), ("ms_sweep", ctypes.c_double),
+                ("ms_finalize", ctypes.c_double), ("pairs", ctypes.c_int64),
+                ("fallback_rows", ctypes.c_int64), ("calls", ctypes.c_int32),
+                ("sweep_launches", ctypes.c_int32), ("refresh_rows", ctypes.c_int32),
+                ("diags_per_lane", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1901_05708_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.mp_aamp.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp]
+    lib.mp_pnorm.argtypes = [vp, i64, i32, dbl, i32, i32, i32, vp, vp, vp]
+    lib.mp_acamp.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp]
+    lib.mp_batch.argtypes = [vp, ctypes.POINTER(MpJob), i32, i32, vp, vp, vp]
+    for f in (lib.mp_aamp, lib.mp_pnorm, lib.mp_acamp, lib.mp_batch):
+        f.restype = ctypes.c_int
+    lib.mp_strerror.argtypes = [ctypes.c_int]
+    lib.mp_strerror.restype = ctypes.c_char_p
+    lib.mp_release.argtypes = []
+    lib.mp_release.restype = None
+    lib.mp_set_profiling.argtypes = [ctypes.c_int]
+    lib.mp_set_profiling.restype = None
+    lib.mp_profile_read.argtypes = [ctypes.POINTER(MpStats)]
+    lib.mp_profile_read.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != MP_OK:
+        raise MpError(rc, load().mp_strerror(rc).decode())
+
+
+def _prec(precision) -> int:
+    if precision in ("fp64", MP_FP64):
+        return MP_FP64
+    if precision in ("fp32", "fp32_refresh", MP_FP32_REFRESH):
+        return MP_FP32_REFRESH
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _series(T, m: int):
+    import torch
+    if not isinstance(T, torch.Tensor) or T.device.type != "cuda":
+        raise TypeError("T must be a torch tensor on a HIP (cuda) device")
+    if T.dtype != torch.float64 or T.dim() != 1:
+        raise TypeError("T must be a 1-D float64 tensor")
+    T = T.contiguous()
+    n = T.shape[0]
+    if not (1 <= m <= n):
+        raise ValueError("need 1 <= m <= len(T)")
+    N = n - m + 1
+    P = torch.empty(N, dtype=torch.float64, device=T.device)
+    I = torch.empty(N, dtype=torch.int64, device=T.device)
+    return T, n, N, P, I
+
+
+def aamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, stream=None):
+    """Pure Euclidean matrix profile (mp_aamp). Returns (P, I) tensors."""
+    T, n, N, P, I = _series(T, m)
+    _check(load().mp_aamp(T.data_ptr(), n, m, excl or 0, _prec(precision), R,
+                          P.data_ptr(), I.data_ptr(), _stream(stream)))
+    return P, I
+
+
+def pnorm(T, m: int, p: float, excl: Optional[int] = None, precision="fp64", R: int = 0,
+          stream=None):
+    """p-norm matrix profile (mp_pnorm), real p >= 1. Returns (P, I)."""
+    T, n, N, P, I = _series(T, m)
+    _check(load().mp_pnorm(T.data_ptr(), n, m, float(p), excl or 0, _prec(precision), R,
+                           P.data_ptr(), I.data_ptr(), _stream(stream)))
+    return P, I
+
+
+def acamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, stream=None):
+    """z-normalized matrix profile (mp_acamp). Returns (P, I)."""
+    T, n, N, P, I = _series(T, m)
+    _check(load().mp_acamp(T.data_ptr(), n, m, excl or 0, _prec(precision), R,
+                           P.data_ptr(), I.data_ptr(), _stream(stream)))
+    return P, I
+
+
+@dataclass
+class Job:
+    n: int
+    m: int
+    kind: int = KIND_AAMP
+    excl: int = 0
+    R: int = 0
+    p: float = 2.0
+
+
+def batch_layout(jobs: Sequence[Job]):
+    """Offsets (t_off, out_off) and totals for concatenated series/outputs."""
+    table = (MpJob * len(jobs))()
+    t_off = out_off = 0
+    for b, jb in enumerate(jobs):
+        table[b] = MpJob(t_off, jb.n, out_off, jb.m, jb.kind, jb.excl, jb.R, jb.p)
+        t_off += jb.n
+        out_off += jb.n - jb.m + 1
+    return table, t_off, out_off
+
+
+def batch(T_cat, jobs: Sequence[Job], precision="fp64", stream=None, out=None):
+    """Matrix profiles of many series in one call (mp_batch). T_cat is the
+    concatenation of the series; returns (P_cat, I_cat) with each job's
+    outputs at its out_off (see batch_layout)."""
+    import torch
+    table, total_n, total_out = batch_layout(jobs)
+    if T_cat.dtype != torch.float64 or T_cat.device.type != "cuda" or T_cat.shape[0] < total_n:
+        raise TypeError("T_cat must be a float64 cuda tensor holding every series")
+    T_cat = T_cat.contiguous()
+    if out is None:
+        P = torch.empty(max(total_out, 1), dtype=torch.float64, device=T_cat.device)
+        I = torch.empty(max(total_out, 1), dtype=torch.int64, device=T_cat.device)
+    else:
+        P, I = out
+    _check(load().mp_batch(T_cat.data_ptr(), table, len(jobs), _prec(precision),
+                           P.data_ptr(), I.data_ptr(), _stream(stream)))
+    return P, I
+
+
+def release():
+    load().mp_release()
+
+
+def set_profiling(on: bool):
+    load().mp_set_profiling(1 if on else 0)
+
+
+def profile_read() -> dict:
+    st = MpStats()
+    _check(load().mp_profile_read(ctypes.byref(st)))
+    return st.as_dict()
+
+
+def pair_count(n: int, m: int, excl: int) -> int:
+    """Admissible unordered pairs (i < j, j - i >= excl) of a series."""
+    N = n - m + 1
+    if N <= excl:
+        return 0
+    k = N - excl
+    return k * (k + 1) // 2
+
+
+def default_excl(m: int) -> int:
+    return (m + 3) // 4

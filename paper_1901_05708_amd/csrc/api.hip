@@ -1,0 +1,433 @@
+// api.hip -- host side of libmp: argument validation, per-device workspace,
+// the planner that picks the sweep kernel and its shape, and the C ABI of
+// include/mp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mp.h"
+#include "mp_internal.h"
+
+using namespace mpk;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local int g_last_code = MP_OK;
+
+int fail(int code, const char *what)
+{
+    g_last_code = code;
+    g_err = what;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *where)
+{
+    g_last_code = MP_EHIP;
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return MP_EHIP;
+}
+
+#define HIP_TRY(expr, where)                     \
+    do {                                         \
+        hipError_t e__ = (expr);                 \
+        if (e__ != hipSuccess) return fail_hip(e__, where); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// per-device workspace (grow-only)
+// ---------------------------------------------------------------------------
+struct Workspace {
+    int64_t cap = 0;           // stream entries (N + STREAM_PAD) the buffers hold
+    double *x = nullptr, *y = nullptr, *z = nullptr;
+    double *mu = nullptr, *invn = nullptr;
+    uint8_t *isconst = nullptr;
+    unsigned long long *keys = nullptr;
+    int32_t *fb_rows = nullptr;
+    int32_t *counters = nullptr;       // [0] fallback count, [1..] spare
+    int64_t band_cap = 0;
+    int64_t *band_start = nullptr;
+    unsigned int *next_item = nullptr;
+    int arch_ok = -1;                  // -1 unknown, 0 no, 1 gfx950
+};
+
+std::mutex g_mu;
+std::vector<Workspace> g_ws;
+
+void free_ws(Workspace &w)
+{
+    hipFree(w.x);
+    hipFree(w.y);
+    hipFree(w.z);
+    hipFree(w.mu);
+    hipFree(w.invn);
+    hipFree(w.isconst);
+    hipFree(w.keys);
+    hipFree(w.fb_rows);
+    hipFree(w.counters);
+    hipFree(w.band_start);
+    hipFree(w.next_item);
+    int arch = w.arch_ok;
+    w = Workspace();
+    w.arch_ok = arch;
+}
+
+int get_ws(Workspace **out, int *dev_out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    Workspace &w = g_ws[dev];
+    if (w.arch_ok < 0) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        w.arch_ok = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 0;
+    }
+    if (!w.arch_ok) return fail(MP_EUNSUPPORTED, "the current HIP device is not a gfx950 GPU");
+    *out = &w;
+    *dev_out = dev;
+    return MP_OK;
+}
+
+template <class T>
+int grow(T **p, size_t count, const char *what)
+{
+    hipFree(*p);
+    *p = nullptr;
+    hipError_t e = hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        return fail(MP_ENOMEM, what);
+    }
+    if (e != hipSuccess) return fail_hip(e, what);
+    return MP_OK;
+}
+
+int ensure_ws(Workspace &w, int64_t N)
+{
+    const int64_t need = N + STREAM_PAD;
+    if (w.cap >= need) return MP_OK;
+    int64_t cap = std::max<int64_t>(need, w.cap + w.cap / 2);
+    free_ws(w);
+    int rc;
+    if ((rc = grow(&w.x, cap, "workspace x")) || (rc = grow(&w.y, cap, "workspace y")) ||
+        (rc = grow(&w.z, cap, "workspace z")) || (rc = grow(&w.mu, cap, "workspace mu")) ||
+        (rc = grow(&w.invn, cap, "workspace invn")) ||
+        (rc = grow(&w.isconst, cap, "workspace const")) ||
+        (rc = grow(&w.keys, cap, "workspace keys")) ||
+        (rc = grow(&w.fb_rows, cap, "workspace fallback")) ||
+        (rc = grow(&w.counters, 64, "workspace counters")) ||
+        (rc = grow(&w.next_item, 64, "workspace counter"))) {
+        free_ws(w);
+        return rc;
+    }
+    w.cap = cap;
+    return MP_OK;
+}
+
+int ensure_bands(Workspace &w, int64_t nbands)
+{
+    if (w.band_cap >= nbands + 1) return MP_OK;
+    int64_t cap = std::max<int64_t>(nbands + 1, 4096);
+    int rc = grow(&w.band_start, cap, "workspace bands");
+    if (rc) {
+        w.band_cap = 0;
+        return rc;
+    }
+    w.band_cap = cap;
+    return MP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+struct EvSet {
+    hipEvent_t ev[4];
+};
+
+struct Prof {
+    bool on = false;
+    std::vector<EvSet> pending;
+    mp_stats acc{};
+};
+std::mutex g_prof_mu;
+Prof g_prof;
+
+int prof_begin(hipStream_t st, EvSet *es, bool *active)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    *active = g_prof.on;
+    if (!*active) return MP_OK;
+    for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&es->ev[k]), "hipEventCreate");
+    HIP_TRY(hipEventRecord(es->ev[0], st), "hipEventRecord");
+    return MP_OK;
+}
+
+void prof_end(const EvSet &es, const mp_stats &cfg)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.pending.push_back(es);
+    g_prof.acc.calls += 1;
+    g_prof.acc.sweep_launches += cfg.sweep_launches;
+    g_prof.acc.pairs += cfg.pairs;
+    g_prof.acc.refresh_rows = cfg.refresh_rows;
+    g_prof.acc.diags_per_lane = cfg.diags_per_lane;
+    g_prof.acc.items = cfg.items;
+}
+
+// ---------------------------------------------------------------------------
+// validation and planning
+// ---------------------------------------------------------------------------
+int32_t index_bits(int64_t N)
+{
+    int32_t b = 1;
+    while (b < 40 && ((int64_t)1 << b) < N) ++b;
+    return b;
+}
+
+int64_t pair_count(int64_t N, int64_t excl)
+{
+    if (N <= excl) return 0;
+    int64_t k = N - excl;
+    return k * (k + 1) / 2;
+}
+
+int validate(const double *T, int64_t n, int32_t m, int32_t precision, int32_t R,
+             const double *P, const int64_t *I)
+{
+    if (!T || !P || !I) return fail(MP_EINVAL, "null pointer argument");
+    if (n < 1) return fail(MP_EINVAL, "n must be >= 1");
+    if (n >= MP_MAX_N) return fail(MP_EINVAL, "n must be < 2^31");
+    if (m < 1 || (int64_t)m > n) return fail(MP_EINVAL, "m must satisfy 1 <= m <= n");
+    if (precision != MP_FP64 && precision != MP_FP32_REFRESH)
+        return fail(MP_EINVAL, "precision must be MP_FP64 or MP_FP32_REFRESH");
+    if (R < 0) return fail(MP_EINVAL, "R must be >= 0");
+    return MP_OK;
+}
+
+int32_t pclass_of(double p)
+{
+    if (p == 1.0) return P_ONE;
+    if (p == 2.0) return P_TWO;
+    if (p == 3.0) return P_THREE;
+    return P_GENERIC;
+}
+
+const char *sweep_choice()
+{
+    const char *e = std::getenv("MP_SWEEP");
+    return e ? e : "auto";
+}
+
+struct Plan {
+    bool band = false;
+    int32_t R = 0;
+    int32_t diags_per_lane = 0;
+    int32_t grid = 0;
+    int64_t nbands = 0;
+};
+
+int make_plan(const Series &s, int32_t R_user, Plan *pl)
+{
+    const int64_t ndiag = s.N - s.excl;
+    Plan p;
+    std::string choice = sweep_choice();
+    p.band = false;  // the band kernel is selected below once available
+    if (choice == "band") p.band = true;
+    if (ndiag <= 0) p.band = false;
+    if (!p.band) {
+        int32_t R = R_user > 0 ? R_user : 1024;
+        // the simple kernel's grid has one row of blocks per segment
+        int64_t minR = (ndiag + 65534) / 65535;
+        if (R < minR) R = (int32_t)minR;
+        p.R = R;
+    }
+    *pl = p;
+    return MP_OK;
+}
+
+int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
+               int32_t precision, int32_t R, double *P, int64_t *I, void *stream)
+{
+    int rc = validate(T, n, m, precision, R, P, I);
+    if (rc) return rc;
+    if (kind == PNORM && !(std::isfinite(p) && p >= 1.0))
+        return fail(MP_EINVAL, "p must be finite and >= 1");
+    if (excl <= 0) excl = (m + 3) / 4;
+    if (kind == PNORM && p == 2.0) kind = AAMP;  // Sec. 3.3: p = 2 is Euclid
+
+    Workspace *w = nullptr;
+    int dev = 0;
+    if ((rc = get_ws(&w, &dev))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = n - m + 1;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if ((rc = ensure_ws(*w, N))) return rc;
+    }
+
+    Series s;
+    std::memset(&s, 0, sizeof(s));
+    s.T = T;
+    s.n = n;
+    s.N = N;
+    s.m = m;
+    s.kind = kind;
+    s.pclass = kind == PNORM ? pclass_of(p) : P_TWO;
+    s.excl = excl;
+    s.p = p;
+    s.gb = index_bits(N);
+    s.x = w->x;
+    s.y = w->y;
+    s.z = w->z;
+    s.mu = w->mu;
+    s.invn = w->invn;
+    s.isconst = w->isconst;
+    s.keys = w->keys;
+    s.fb_count = w->counters;
+
+    Fallback fb;
+    fb.count = w->counters;
+    fb.rows = w->fb_rows;
+    fb.capacity = (int32_t)std::min<int64_t>(N, INT32_MAX);
+
+    Plan pl;
+    if ((rc = make_plan(s, R, &pl))) return rc;
+
+    EvSet es;
+    bool prof = false;
+    if ((rc = prof_begin(st, &es, &prof))) return rc;
+
+    HIP_TRY(launch_prep(s, st), "prep launch");
+    if (prof) HIP_TRY(hipEventRecord(es.ev[1], st), "hipEventRecord");
+    HIP_TRY(launch_sweep_simple(s, pl.R, st), "sweep launch");
+    if (prof) HIP_TRY(hipEventRecord(es.ev[2], st), "hipEventRecord");
+    HIP_TRY(launch_finalize(s, fb, P, I, st), "finalize launch");
+    HIP_TRY(launch_fallback(s, fb, P, I, st), "fallback launch");
+    if (prof) {
+        HIP_TRY(hipEventRecord(es.ev[3], st), "hipEventRecord");
+        mp_stats cfg{};
+        cfg.pairs = pair_count(N, excl);
+        cfg.sweep_launches = 1;
+        cfg.refresh_rows = pl.R;
+        cfg.diags_per_lane = pl.band ? pl.diags_per_lane : 0;
+        cfg.items = 0;
+        prof_end(es, cfg);
+    }
+    g_last_code = MP_OK;
+    return MP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mp_aamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precision, int32_t R,
+            double *P, int64_t *I, void *stream)
+{
+    return run_series(T, n, m, AAMP, 2.0, excl, precision, R, P, I, stream);
+}
+
+int mp_pnorm(const double *T, int64_t n, int32_t m, double p, int32_t excl, int32_t precision,
+             int32_t R, double *P, int64_t *I, void *stream)
+{
+    return run_series(T, n, m, PNORM, p, excl, precision, R, P, I, stream);
+}
+
+int mp_acamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precision, int32_t R,
+             double *P, int64_t *I, void *stream)
+{
+    return run_series(T, n, m, ACAMP, 2.0, excl, precision, R, P, I, stream);
+}
+
+int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
+             double *P_cat, int64_t *I_cat, void *stream)
+{
+    if (!T_cat || !jobs || !P_cat || !I_cat) return fail(MP_EINVAL, "null pointer argument");
+    if (njobs < 0) return fail(MP_EINVAL, "njobs must be >= 0");
+    for (int32_t b = 0; b < njobs; ++b) {
+        const mp_job &jb = jobs[b];
+        if (jb.t_off < 0 || jb.out_off < 0) return fail(MP_EINVAL, "negative job offset");
+        if (jb.kind < MP_KIND_AAMP || jb.kind > MP_KIND_ACAMP)
+            return fail(MP_EINVAL, "job kind must be MP_KIND_*");
+    }
+    for (int32_t b = 0; b < njobs; ++b) {
+        const mp_job &jb = jobs[b];
+        int rc = run_series(T_cat + jb.t_off, jb.n, jb.m, jb.kind, jb.p, jb.excl, precision, jb.R,
+                            P_cat + jb.out_off, I_cat + jb.out_off, stream);
+        if (rc) return rc;
+    }
+    return MP_OK;
+}
+
+const char *mp_strerror(int code)
+{
+    static thread_local std::string msg;
+    const char *base;
+    switch (code) {
+    case MP_OK: base = "success"; break;
+    case MP_EINVAL: base = "invalid argument"; break;
+    case MP_ENOMEM: base = "device allocation failed"; break;
+    case MP_EHIP: base = "HIP runtime error"; break;
+    case MP_EUNSUPPORTED: base = "unsupported device"; break;
+    default: base = "unknown error code"; break;
+    }
+    msg = base;
+    if (code != MP_OK && code == g_last_code && !g_err.empty()) msg += ": " + g_err;
+    return msg.c_str();
+}
+
+void mp_release(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (size_t d = 0; d < g_ws.size(); ++d) {
+        if (g_ws[d].cap == 0 && g_ws[d].band_cap == 0) continue;
+        (void)hipSetDevice((int)d);
+        (void)hipDeviceSynchronize();
+        free_ws(g_ws[d]);
+    }
+    (void)hipSetDevice(cur);
+}
+
+void mp_set_profiling(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &es : g_prof.pending)
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(es.ev[k]);
+    g_prof.pending.clear();
+    g_prof.acc = mp_stats{};
+    g_prof.on = on != 0;
+}
+
+int mp_profile_read(mp_stats *out)
+{
+    if (!out) return fail(MP_EINVAL, "null pointer argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &es : g_prof.pending) {
+        float a = 0.f, b = 0.f, c = 0.f;
+        HIP_TRY(hipEventSynchronize(es.ev[3]), "hipEventSynchronize");
+        HIP_TRY(hipEventElapsedTime(&a, es.ev[0], es.ev[1]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&b, es.ev[1], es.ev[2]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&c, es.ev[2], es.ev[3]), "hipEventElapsedTime");
+        g_prof.acc.ms_prep += a;
+        g_prof.acc.ms_sweep += b;
+        g_prof.acc.ms_finalize += c;
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(es.ev[k]);
+    }
+    g_prof.pending.clear();
+    *out = g_prof.acc;
+    return MP_OK;
+}
+
+}  // extern "C"

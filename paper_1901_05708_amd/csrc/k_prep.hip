@@ -1,0 +1,106 @@
+// k_prep.hip -- per-window preparation that sits outside the sweep's inner
+// loop: the O(m (n - m)) part of the method (Secs. 3.4 and 4.3), computed once
+// per window in FP64 instead of once per diagonal.
+#include "keys.h"
+#include "mp_internal.h"
+
+namespace mpk {
+
+// Window mean, exact all-equal flag and inverse centred norm
+// invn_j = 1 / sqrt(sum_l (t_{j+l} - mu_j)^2) = 1 / (sqrt(m) sigma_j) with the
+// population standard deviation of App. A, computed directly in two passes per
+// window (no running sums, so no cancellation over long series). A constant
+// window gets invn = 0; its z-normalized distance to anything is infinite
+// (Sec. 1) and the sweep never lets it win.
+__global__ void k_window_stats(Series s)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= s.N) return;
+    const double *w = s.T + j;
+    const int m = s.m;
+    double sum = 0.0;
+    bool same = true;
+    const double w0 = w[0];
+    for (int l = 0; l < m; ++l) {
+        double v = w[l];
+        sum += v;
+        same = same && (v == w0);
+    }
+    const double mu = sum / (double)m;
+    double ss = 0.0;
+    for (int l = 0; l < m; ++l) {
+        double d = w[l] - mu;
+        ss = fma(d, d, ss);
+    }
+    s.mu[j] = mu;
+    s.isconst[j] = same ? 1 : 0;
+    s.invn[j] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
+}
+
+// Per-window difference streams used by the O(1) diagonal updates, and the
+// key array reset. Entry j describes what changes when a window slides from
+// start j-1 to start j: sample t_{j-1} leaves, sample t_{j+m-1} enters.
+//
+//  AAMP (Lemma 1): D^2_{i,j} - D^2_{i-1,j-1}
+//        = (t_{i+m-1} - t_{j+m-1})^2 - (t_{i-1} - t_{j-1})^2
+//        = (u_i - u_j)(v_i - v_j),  u = t_{.+m-1} - t_{.-1}, v = t_{.+m-1} + t_{.-1}
+//  p-norm (Lemma 2): |a_i - a_j|^p - |b_i - b_j|^p,  a = t_{.+m-1}, b = t_{.-1}
+//  ACAMP: the centred cross sum cov_{i,j} = sum_l (t_{i+l}-mu_i)(t_{j+l}-mu_j)
+//        (the numerator C - A B / m of Lemma 3) obeys
+//        cov_{i,j} = cov_{i-1,j-1} + df_i dg_j + df_j dg_i
+//        with df = (t_{.+m-1} - t_{.-1}) / 2 and
+//        dg_j = (t_{j+m-1} - mu_j) + (t_{j-1} - mu_{j-1}).
+//        Stored with z_j = -invn_j so that -rho = cov invn_i z_j.
+// Entries j >= N hold sentinels that make every pair touching them lose.
+__global__ void k_streams(Series s)
+{
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = s.N + STREAM_PAD;
+    if (j >= total) return;
+    if (j < s.N) s.keys[j] = KEY_NONE;
+    if (j == 0) *s.fb_count = 0;
+    const int m = s.m;
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (j >= s.N) {
+        if (s.kind == AAMP) {
+            x = SENT_EUCLID;
+            y = SENT_EUCLID;
+        } else if (s.kind == PNORM) {
+            x = (s.pclass == P_ONE) ? SENT_P1 : (s.pclass == P_THREE ? SENT_P3 : 0.0);
+            y = 0.0;
+        }
+    } else if (j >= 1) {
+        const double tin = s.T[j + m - 1];
+        const double tout = s.T[j - 1];
+        if (s.kind == AAMP) {
+            x = tin - tout;
+            y = tin + tout;
+        } else if (s.kind == PNORM) {
+            x = tin;
+            y = tout;
+        } else {
+            x = 0.5 * (tin - tout);
+            y = (tin - s.mu[j]) + (tout - s.mu[j - 1]);
+        }
+    }
+    if (s.kind == ACAMP && j < s.N) z = -s.invn[j];
+    s.x[j] = x;
+    s.y[j] = y;
+    if (s.kind == ACAMP) s.z[j] = z;
+}
+
+hipError_t launch_prep(const Series &s, hipStream_t st)
+{
+    const int B = 256;
+    if (s.kind == ACAMP) {
+        unsigned g = (unsigned)((s.N + B - 1) / B);
+        hipLaunchKernelGGL(k_window_stats, dim3(g), dim3(B), 0, st, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    unsigned g = (unsigned)((s.N + STREAM_PAD + B - 1) / B);
+    hipLaunchKernelGGL(k_streams, dim3(g), dim3(B), 0, st, s);
+    return hipGetLastError();
+}
+
+}  // namespace mpk

@@ -1,0 +1,50 @@
+"""Acceptance check of a GPU profile against the oracle (test helper).
+
+Per row i, with rtol / atol the tolerance of the precision mode:
+  1. both +inf with index -1, or both finite;
+  2. |P - P_ref| <= rtol * P_ref + atol;
+  3. I == I_ref, or the row is a near tie (runner-up within the tolerance of
+     the best) and the reported index is admissible with a directly computed
+     distance within the tolerance of the best;
+  4. P equals the direct distance of (i, I) (checked on the mismatched rows
+     and on a sample of the others).
+"""
+import numpy as np
+
+import oracle
+
+
+def check_profile(T, m, kind, p, excl, P, I, Pref, Iref, Qref, rtol, atol, rows=None,
+                  sample=64, label=""):
+    P = np.asarray(P, dtype=np.float64)
+    I = np.asarray(I, dtype=np.int64)
+    rows = np.arange(len(Pref)) if rows is None else np.asarray(rows)
+    inf_g, inf_r = np.isinf(P), np.isinf(Pref)
+    bad = np.nonzero(inf_g != inf_r)[0]
+    assert bad.size == 0, f"{label}: finiteness differs at rows {rows[bad[:10]]}"
+    assert np.all(I[inf_r] == -1), f"{label}: infinite rows must report index -1"
+    fin = ~inf_r
+    err = np.abs(P[fin] - Pref[fin])
+    tol = rtol * Pref[fin] + atol
+    badv = np.nonzero(err > tol)[0]
+    assert badv.size == 0, (f"{label}: {badv.size} values off, worst rel "
+                            f"{np.max(err / np.maximum(Pref[fin], 1e-300)):.3e} at rows "
+                            f"{rows[np.nonzero(fin)[0][badv[:10]]]}")
+    mism = np.nonzero(fin & (I != Iref))[0]
+    for r in mism:
+        i, ig = int(rows[r]), int(I[r])
+        near = (Qref[r] - Pref[r]) <= rtol * Pref[r] + atol
+        assert near, (f"{label}: row {i}: index {ig} != {Iref[r]} and runner-up gap "
+                      f"{(Qref[r] - Pref[r]) / max(Pref[r], 1e-300):.3e} exceeds rtol")
+        assert abs(i - ig) >= excl and 0 <= ig
+        d = oracle.distance(T, m, i, ig, kind, p)
+        assert d <= Pref[r] * (1 + rtol) + atol, f"{label}: row {i}: reported pair is not near-best"
+    rng = np.random.default_rng(0)
+    finrows = np.nonzero(fin)[0]
+    pick = np.unique(np.concatenate([mism, rng.choice(finrows, size=min(sample, finrows.size),
+                                                      replace=False)])) if finrows.size else mism
+    for r in pick:
+        d = oracle.distance(T, m, int(rows[r]), int(I[r]), kind, p)
+        assert abs(d - P[r]) <= 1e-12 * max(d, 1e-300) + 1e-12, \
+            f"{label}: row {rows[r]}: P is not the distance of the reported pair"
+    return {"rows": len(rows), "index_mismatch": int(mism.size)}

@@ -1,0 +1,74 @@
+"""CPU-side checks of the C ABI: the library builds and exports every symbol
+that include/mp.h declares; argument errors are rejected before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1901_05708_amd as mp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mp.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mp_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mp.LIB_PATH):
+        from paper_1901_05708_amd import build
+        build.build()
+    return mp.load()
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for f in ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_strerror", "mp_release"):
+        assert f in names
+    assert set(mp.EXPORTED) <= set(names)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"libmp.so does not export {name}"
+
+
+def test_invalid_arguments_rejected_without_gpu(lib):
+    vp = ctypes.c_void_p
+    dummy = vp(16)   # never dereferenced: validation fails first
+    # null pointers
+    assert lib.mp_aamp(None, 100, 10, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    # bad m
+    assert lib.mp_aamp(dummy, 100, 0, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_aamp(dummy, 100, 101, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    # bad n
+    assert lib.mp_acamp(dummy, 0, 1, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_acamp(dummy, 1 << 31, 4, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    # bad precision / R
+    assert lib.mp_aamp(dummy, 100, 10, 0, 7, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_aamp(dummy, 100, 10, 0, 0, -1, dummy, dummy, None) == mp.MP_EINVAL
+    # bad p
+    assert lib.mp_pnorm(dummy, 100, 10, 0.5, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_pnorm(dummy, 100, 10, float("inf"), 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_pnorm(dummy, 100, 10, float("nan"), 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    msg = lib.mp_strerror(mp.MP_EINVAL).decode()
+    assert "invalid argument" in msg
+    # batch: bad job table
+    jobs = (mp.MpJob * 1)()
+    jobs[0] = mp.MpJob(0, 100, 0, 10, 9, 0, 0, 2.0)
+    assert lib.mp_batch(dummy, jobs, 1, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_batch(None, jobs, 1, 0, dummy, dummy, None) == mp.MP_EINVAL
+
+
+def test_strerror_never_null(lib):
+    for code in (0, -1, -2, -3, -4, 12345):
+        assert isinstance(lib.mp_strerror(code), bytes)
+
+
+def test_profile_read_rejects_null(lib):
+    assert lib.mp_profile_read(None) == mp.MP_EINVAL
