@@ -187,10 +187,12 @@ void prof_end(const EvSet &es, const mp_stats &cfg)
 // ---------------------------------------------------------------------------
 // validation and planning
 // ---------------------------------------------------------------------------
+// Index bits of a global key: 2^gb > N, so the all-ones index field never
+// names a window and can mark an illegal winner.
 int32_t index_bits(int64_t N)
 {
     int32_t b = 1;
-    while (b < 40 && ((int64_t)1 << b) < N) ++b;
+    while (b < 40 && ((int64_t)1 << b) <= N) ++b;
     return b;
 }
 
@@ -234,17 +236,65 @@ struct Plan {
     int32_t diags_per_lane = 0;
     int32_t grid = 0;
     int64_t nbands = 0;
+    int64_t items = 0;
 };
 
-int make_plan(const Series &s, int32_t R_user, Plan *pl)
+struct DevInfo {
+    int cus = 0;
+};
+std::vector<DevInfo> g_dev;
+
+int device_cus(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    if (g_dev[dev].cus == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+        g_dev[dev].cus = prop.multiProcessorCount;
+    }
+    return g_dev[dev].cus;
+}
+
+int64_t segments_total(int64_t N, int64_t excl, int64_t W, int64_t R, int64_t *nbands)
+{
+    const int64_t nd = N - excl;
+    const int64_t nb = (nd + W - 1) / W;
+    int64_t t = 0;
+    for (int64_t b = 0; b < nb; ++b) t += (nd - b * W + R - 1) / R;
+    *nbands = nb;
+    return t;
+}
+
+// Kernel and shape. The band kernel needs at least one full band; the refresh
+// interval R (rows per segment) defaults to the value that gives every wave
+// slot of the persistent grid a few items, clamped to [256, 4096] rows: the
+// exact restart costs 2m operations per diagonal per segment, and longer
+// segments let FP64 round-off drift further between restarts.
+int make_plan(const Series &s, int32_t R_user, int dev, Plan *pl)
 {
     const int64_t ndiag = s.N - s.excl;
     Plan p;
     std::string choice = sweep_choice();
-    p.band = false;  // the band kernel is selected below once available
-    if (choice == "band") p.band = true;
+    const int32_t kd = 8;
+    const int64_t W = 64 * kd;
+    p.band = band_supported(s) && ndiag >= W / 2 && choice != "simple";
+    if (choice == "band" && band_supported(s) && ndiag > 0) p.band = true;
     if (ndiag <= 0) p.band = false;
-    if (!p.band) {
+    if (p.band) {
+        p.diags_per_lane = kd;
+        const int64_t slots = (int64_t)device_cus(dev) * band_blocks_per_cu(s, kd);
+        int64_t R = R_user;
+        if (R <= 0) {
+            const int64_t pairs = pair_count(s.N, s.excl);
+            R = pairs / std::max<int64_t>(1, W * slots * 4);
+            R = std::min<int64_t>(4096, std::max<int64_t>(256, R));
+        }
+        R = ((R + kd - 1) / kd) * kd;   // whole blocks of steps
+        p.R = (int32_t)std::min<int64_t>(R, INT32_MAX / 2);
+        p.items = segments_total(s.N, s.excl, W, p.R, &p.nbands);
+        p.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(slots, p.items));
+    } else {
         int32_t R = R_user > 0 ? R_user : 1024;
         // the simple kernel's grid has one row of blocks per segment
         int64_t minR = (ndiag + 65534) / 65535;
@@ -301,7 +351,21 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
     fb.capacity = (int32_t)std::min<int64_t>(N, INT32_MAX);
 
     Plan pl;
-    if ((rc = make_plan(s, R, &pl))) return rc;
+    if ((rc = make_plan(s, R, dev, &pl))) return rc;
+    BandPlan bp;
+    std::memset(&bp, 0, sizeof(bp));
+    if (pl.band) {
+        if (pl.items >= (int64_t)INT32_MAX) return fail(MP_EINVAL, "series too long for this refresh interval");
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            if ((rc = ensure_bands(*w, pl.nbands))) return rc;
+        }
+        bp.band_width = 64 * pl.diags_per_lane;
+        bp.seg_rows = pl.R;
+        bp.nbands = (int32_t)pl.nbands;
+        bp.band_start = w->band_start;
+        bp.next_item = w->next_item;
+    }
 
     EvSet es;
     bool prof = false;
@@ -309,7 +373,12 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
 
     HIP_TRY(launch_prep(s, st), "prep launch");
     if (prof) HIP_TRY(hipEventRecord(es.ev[1], st), "hipEventRecord");
-    HIP_TRY(launch_sweep_simple(s, pl.R, st), "sweep launch");
+    if (pl.band) {
+        HIP_TRY(launch_plan(s, bp, st), "plan launch");
+        HIP_TRY(launch_sweep_band(s, bp, pl.diags_per_lane, pl.grid, st), "sweep launch");
+    } else {
+        HIP_TRY(launch_sweep_simple(s, pl.R, st), "sweep launch");
+    }
     if (prof) HIP_TRY(hipEventRecord(es.ev[2], st), "hipEventRecord");
     HIP_TRY(launch_finalize(s, fb, P, I, st), "finalize launch");
     HIP_TRY(launch_fallback(s, fb, P, I, st), "fallback launch");
@@ -320,7 +389,7 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
         cfg.sweep_launches = 1;
         cfg.refresh_rows = pl.R;
         cfg.diags_per_lane = pl.band ? pl.diags_per_lane : 0;
-        cfg.items = 0;
+        cfg.items = (int32_t)std::min<int64_t>(pl.items, INT32_MAX);
         prof_end(es, cfg);
     }
     g_last_code = MP_OK;

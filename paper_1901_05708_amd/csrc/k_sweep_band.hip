@@ -1,0 +1,513 @@
+// k_sweep_band.hip -- the diagonal sweep, wavefront-native.
+//
+// What is computed is Algorithms 1-3: along every diagonal k = j - i the
+// pre-root distance of (i, j) follows from that of (i-1, j-1) in O(1)
+// (Lemma 1 / Lemma 2 / the centred form of Lemma 3), and every pair updates the
+// minimum of its row i and of its column j. How it is laid out here:
+//
+//  * A work item is a band of 64*KD consecutive diagonals [k_lo, k_lo + 64 KD)
+//    times a segment of rows [i0, i1). One wavefront owns one item at a time
+//    (persistent grid, items taken from an atomic counter).
+//  * Lane l owns the KD diagonals k_lo + KD l + d. All 64 lanes step through
+//    the rows together, so the row operands are wave-uniform (scalar loads) and
+//    the column operands of a step are KD-strided in the column stream.
+//  * Each item starts with the exact FP64 sums of its first row (the refresh),
+//    then runs the O(1) recurrence for the remaining rows.
+//  * Column operands come from an LDS ring: the stream entries of the item's
+//    columns are staged once (coalesced, one block of KD entries per KD steps,
+//    fetched a block ahead) and each step every lane reads the one entry that
+//    enters its register window of KD columns.
+//  * Minima are kept as packed keys: the double being minimised with its low
+//    log2(64 KD) mantissa bits replaced by the wave-local diagonal index, so one
+//    v_min_f64 keeps value and argument together.
+//    - row i: min over the lane's KD diagonals in registers, then across the
+//      64 lanes through a small LDS transpose every 8 rows, then one global
+//      atomicMin per row and item;
+//    - column j: the lane keeps a rotating accumulator per column of its
+//      window; after a column's last diagonal in lane l it moves to lane l-1
+//      (one DPP wave shift per step) and when it leaves lane 0 it is complete
+//      for the item and goes to the global keys with one atomicMin.
+//  * Pairs past the end of the series read sentinel stream entries (see
+//    k_prep) and lose every comparison; rows and columns outside the item or
+//    the series are never written.
+//
+// Local column numbering: c = j - (i0 + k_lo). At step tau (row i0 + 1 + tau)
+// lane l diagonal d touches c = tau + 1 + KD l + d; the entering column of a
+// step (d = KD - 1) is c = tau + KD (l + 1). Step tau = -1 is the first row.
+#include "keys.h"
+#include "mp_internal.h"
+
+namespace mpk {
+
+namespace {
+
+constexpr int NRB = 8;  // rows per LDS transpose batch
+
+template <int KD>
+struct Log2;
+template <>
+struct Log2<8> {
+    static constexpr int v = 3;
+};
+template <>
+struct Log2<16> {
+    static constexpr int v = 4;
+};
+
+// XOR term of the ring swizzle for column block u = c / KD: element c is
+// stored at c ^ g(u), a permutation inside each aligned block of KD elements.
+// One step's reads (consecutive u, same offset in the block) land on distinct
+// bank pairs; within a block of steps a lane's address changes by one XOR.
+template <int KD>
+__device__ __forceinline__ int gxor(int u)
+{
+    return (u >> (5 - Log2<KD>::v)) & (KD - 1);
+}
+
+template <int KD>
+__device__ __forceinline__ int ring_pos(int c)
+{
+    return c ^ gxor<KD>(c >> Log2<KD>::v);
+}
+
+__device__ __forceinline__ double fmin_key(double a, double b) { return __builtin_fmin(a, b); }
+
+// Replace the low index bits of a key (double bits) by w.
+__device__ __forceinline__ double make_key(double v, uint32_t notmask, uint32_t w)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    uint32_t lo = ((uint32_t)b & notmask) | w;
+    uint32_t hi = (uint32_t)(b >> 32);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// DPP wave_shl:1 -- lane l receives lane l+1's key; lane 63 receives +inf
+// (high word 0x7FF00000 kept from `old`, low word zero-filled by bound_ctrl).
+__device__ __forceinline__ double shift_down_inf(double v)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x130, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_update_dpp((int)0x7FF00000, (int)(uint32_t)(b >> 32), 0x130, 0xF, 0xF,
+                                         false);
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+template <int PC>
+__device__ __forceinline__ double pw(double d)
+{
+    double a = fabs(d);
+    if (PC == P_ONE) return a;
+    return a * a * a;  // P_THREE
+}
+
+__device__ __forceinline__ double to_minimised(int kind, double v)
+{
+    // AAMP / p-norm minimise the pre-root sum itself; ACAMP keys hold -rho and
+    // the global key holds 1 - rho = DZ^2 / 2m (Lemma 3).
+    return kind == ACAMP ? 1.0 + v : v;
+}
+
+__device__ __forceinline__ bool flushable(int kind, double v)
+{
+    // untouched accumulators (+inf) and sentinel sums never reach the keys
+    return kind == ACAMP ? (v < 1e300) : (v < 1e190);
+}
+
+// Wave-uniform reads go through the constant address space so that they
+// become scalar loads (the data is read-only for the whole launch).
+typedef const __attribute__((address_space(4))) double cdouble;
+typedef const __attribute__((address_space(4))) int64_t cint64;
+__device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)p; }
+__device__ __forceinline__ cint64 *as_const(const int64_t *p) { return (cint64 *)p; }
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+}  // namespace
+
+template <int KIND, int PC, int KD>
+__global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
+{
+    constexpr int WD = 64 * KD;          // diagonals per item
+    constexpr int RING = WD;             // ring entries per field
+    constexpr int NF = (KIND == ACAMP) ? 3 : 2;
+
+    __shared__ double ring[NF][RING];
+    __shared__ double rowbuf[NRB * 64];
+    __shared__ double colout[64];
+
+    const int lane = threadIdx.x;
+    const int64_t N = s.N;
+    const uint32_t notmask = ~(uint32_t)(WD - 1);
+    const unsigned long long gmask = (1ull << s.gb) - 1ull;
+    const double INF = __longlong_as_double(0x7FF0000000000000ll);
+    const int m = s.m;
+
+    uint32_t wd[KD];
+#pragma unroll
+    for (int d = 0; d < KD; ++d) wd[d] = (uint32_t)(lane * KD + d);
+
+    cint64 *band_start = as_const(bp.band_start);
+    const int64_t total = band_start[bp.nbands];
+    cdouble *Tc = as_const(s.T);
+    cdouble *xc = as_const(s.x);
+    cdouble *yc = as_const(s.y);
+    cdouble *zc = as_const(s.z);
+
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = (int)atomicAdd(bp.next_item, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if ((int64_t)item >= total) break;
+
+        // band of this item: band_start[b] <= item < band_start[b + 1]
+        int lo = 0, hi = bp.nbands;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (band_start[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const int64_t k_lo = uniform64((int64_t)s.excl + (int64_t)lo * WD);
+        const int64_t i0 = uniform64(((int64_t)item - band_start[lo]) * bp.seg_rows);
+        const int64_t i1 = uniform64(min(i0 + (int64_t)bp.seg_rows, N - k_lo));
+        const int nsteps = (int)(i1 - i0) - 1;      // recurrence steps after the first row
+        const int64_t cb = i0 + k_lo;               // stream index of local column 0
+
+        // ---- exact FP64 start values of the first row (the refresh) ----------
+        double S[KD];
+        {
+            const int64_t jb = cb + (int64_t)KD * lane;   // this lane's first column
+            const int64_t tmax = s.n - 1;
+            double acc[KD], win[KD], muj[KD];
+            const double mui = (KIND == ACAMP) ? as_const(s.mu)[i0] : 0.0;
+#pragma unroll
+            for (int d = 0; d < KD; ++d) {
+                acc[d] = 0.0;
+                win[d] = 0.0;
+                muj[d] = (KIND == ACAMP) ? s.mu[min(jb + d, N - 1)] : 0.0;
+            }
+#pragma unroll
+            for (int d = 0; d < KD - 1; ++d) win[d] = s.T[min(jb + d, tmax)];
+            for (int l0 = 0; l0 < m; l0 += KD) {
+#pragma unroll
+                for (int q = 0; q < KD; ++q) {
+                    const int l = l0 + q;
+                    if (l < m) {
+                        win[(q + KD - 1) % KD] = s.T[min(jb + l + KD - 1, tmax)];
+                        const double tr = Tc[i0 + l];
+#pragma unroll
+                        for (int d = 0; d < KD; ++d) {
+                            const double w = win[(q + d) % KD];
+                            if (KIND == AAMP) {
+                                const double e = tr - w;
+                                acc[d] = fma(e, e, acc[d]);
+                            } else if (KIND == PNORM) {
+                                acc[d] += pw<PC>(tr - w);
+                            } else {
+                                acc[d] = fma(tr - mui, w - muj[d], acc[d]);
+                            }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < KD; ++d) {
+                const bool valid = (jb + d) <= N - 1;
+                S[d] = valid ? acc[d] : (KIND == ACAMP ? 0.0 : SENT_INIT);
+            }
+        }
+
+        // ---- stage the column streams in the LDS ring: local columns [0, RING)
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RING / 64; ++q) {
+            const int c = lane + 64 * q;
+            const int e = ring_pos<KD>(c);
+            ring[0][e] = s.x[cb + c];
+            ring[1][e] = s.y[cb + c];
+            if (KIND == ACAMP) ring[2][e] = s.z[cb + c];
+        }
+        __syncthreads();
+
+        // register window of column operands: slot c % KD holds local column c
+        // of this lane's window; slots 1..KD-1 are preloaded for tau = 0
+        double cx[KD], cy[KD], cz[KD];
+#pragma unroll
+        for (int d = 0; d < KD; ++d) {
+            cx[d] = 0.0;
+            cy[d] = 0.0;
+            cz[d] = 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < KD - 1; ++d) {
+            const int c = KD * lane + 1 + d;
+            const int e = ring_pos<KD>(c);
+            cx[(1 + d) % KD] = ring[0][e];
+            cy[(1 + d) % KD] = ring[1][e];
+            if (KIND == ACAMP) cz[(1 + d) % KD] = ring[2][e];
+        }
+
+        double colacc[KD];
+#pragma unroll
+        for (int d = 0; d < KD; ++d) colacc[d] = INF;
+
+        // -------------------------------------------------------------------
+        // one step: keys of the current values, row minimum into the LDS
+        // transpose, column minima into the rotating accumulators, then the
+        // column whose last diagonal in this lane was d = 0 moves one lane down.
+        // The accumulator of diagonal d lives in slot (sbase + d) % KD.
+        auto reduce_step = [&](int tau, int sbase, const double (&v)[KD]) {
+            double rowmin = INF;
+#pragma unroll
+            for (int d = 0; d < KD; ++d) {
+                const double key = make_key(v[d], notmask, wd[d]);
+                rowmin = fmin_key(rowmin, key);
+                colacc[(sbase + d) % KD] = fmin_key(colacc[(sbase + d) % KD], key);
+            }
+            rowbuf[((tau + 1) & (NRB - 1)) * 64 + lane] = rowmin;
+            const double done = colacc[sbase % KD];
+            if (lane == 0) colout[(tau + 1) & 63] = done;
+            colacc[sbase % KD] = shift_down_inf(done);
+        };
+
+        // LDS transpose flush of the rows whose slots are 0..cnt-1; slot 0
+        // holds row rbase.
+        auto flush_rows = [&](int64_t rbase, int cnt) {
+            __syncthreads();
+            const int r = lane & (NRB - 1);
+            const int g = lane >> 3;
+            double v = INF;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v = fmin_key(v, rowbuf[r * 64 + g * 8 + q]);
+            v = fmin_key(v, __shfl_xor(v, 8));
+            v = fmin_key(v, __shfl_xor(v, 16));
+            v = fmin_key(v, __shfl_xor(v, 32));
+            const int64_t row = rbase + r;
+            if (g == 0 && r < cnt && row < i1 && flushable(KIND, v)) {
+                const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
+                const int64_t j = row + k_lo + (int64_t)(kb & (uint64_t)(WD - 1));
+                const unsigned long long idx = (j < N) ? (unsigned long long)j : gmask;
+                atomicMin(&s.keys[row], pack_key(to_minimised(KIND, v), idx, gmask));
+            }
+            __syncthreads();
+        };
+
+        // flush the columns that left lane 0; colout entry c % 64 holds local
+        // column c, for the cnt <= 64 columns c0 .. c0 + cnt - 1 (batches are
+        // 1..64, 65..128, ..., so entries never collide before their flush).
+        auto flush_cols = [&](int c0, int cnt) {
+            __syncthreads();
+            if (lane < cnt) {
+                const int c = c0 + lane;
+                const double v = colout[c & 63];
+                const int64_t j = cb + c;
+                if (j < N && flushable(KIND, v)) {
+                    const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
+                    const int64_t i = j - k_lo - (int64_t)(kb & (uint64_t)(WD - 1));
+                    atomicMin(&s.keys[j], pack_key(to_minimised(KIND, v), (unsigned long long)i, gmask));
+                }
+            }
+            __syncthreads();
+        };
+
+        // ---- first row (tau = -1): start values only ------------------------
+        {
+            double v[KD];
+            const double rinv0 = (KIND == ACAMP) ? -zc[i0] : 0.0;
+            const int64_t jb = cb + (int64_t)KD * lane;
+#pragma unroll
+            for (int d = 0; d < KD; ++d)
+                v[d] = (KIND == ACAMP) ? S[d] * rinv0 * s.z[jb + d] : S[d];
+            reduce_step(-1, 0, v);
+        }
+        flush_cols(0, 1);   // column 0 has only the first row's pair
+
+        // ---- recurrence, KD steps per unrolled block --------------------------
+        // Block tb needs local columns [tb + RING, tb + RING + KD) in the ring;
+        // lanes < KD fetch each block one block ahead.
+        const int bl = min(lane, KD - 1);
+        double bx = s.x[cb + RING + bl];
+        double by = s.y[cb + RING + bl];
+        double bz = (KIND == ACAMP) ? s.z[cb + RING + bl] : 0.0;
+        int tb = 0;
+        for (; tb < nsteps; tb += KD) {
+            tb = __builtin_amdgcn_readfirstlane(tb);
+            // row operands of this block: rows i0 + 1 + tb + q, q < KD
+            const int64_t rb = uniform64(i0 + 1 + tb);
+            cdouble *xr = xc + rb;
+            cdouble *yr = yc + rb;
+            cdouble *zr = zc + rb;
+            __syncthreads();
+            if (lane < KD) {
+                const int e = ring_pos<KD>((tb + RING + lane) & (RING - 1));
+                ring[0][e] = bx;
+                ring[1][e] = by;
+                if (KIND == ACAMP) ring[2][e] = bz;
+            }
+            __syncthreads();
+            {
+                const int64_t c = cb + tb + KD + RING + bl;
+                bx = s.x[c];
+                by = s.y[c];
+                if (KIND == ACAMP) bz = s.z[c];
+            }
+            // this block's entering columns are tb + KD (lane + 1) + q, all in
+            // the aligned column block u = tb / KD + lane + 1
+            const int ublk = (tb >> Log2<KD>::v) + lane + 1;
+            const int ebase = ((ublk * KD) & (RING - 1)) ^ gxor<KD>(ublk);
+#pragma unroll
+            for (int q = 0; q < KD; ++q) {
+                const int tau = tb + q;
+                {
+                    const int e = ebase ^ q;
+                    cx[q] = ring[0][e];
+                    cy[q] = ring[1][e];
+                    if (KIND == ACAMP) cz[q] = ring[2][e];
+                }
+                const double rx = xr[q];
+                const double ry = yr[q];
+                double rinv = 0.0;
+                if (KIND == ACAMP) rinv = -zr[q];
+                double v[KD];
+#pragma unroll
+                for (int d = 0; d < KD; ++d) {
+                    const int sl = (q + 1 + d) % KD;
+                    if (KIND == AAMP) {
+                        S[d] = fma(rx - cx[sl], ry - cy[sl], S[d]);
+                        v[d] = S[d];
+                    } else if (KIND == PNORM) {
+                        S[d] += pw<PC>(rx - cx[sl]) - pw<PC>(ry - cy[sl]);
+                        v[d] = S[d];
+                    } else {
+                        S[d] = fma(rx, cy[sl], S[d]);
+                        S[d] = fma(cx[sl], ry, S[d]);
+                        v[d] = S[d] * rinv * cz[sl];
+                    }
+                }
+                reduce_step(tau, q + 1, v);
+                // tb is a multiple of KD and NRB divides KD: (tau + 1) % NRB == (q + 1) % NRB
+                if (((q + 1) & (NRB - 1)) == NRB - 1) flush_rows(i0 + tau + 2 - NRB, NRB);
+            }
+            // the column of step tau is tau + 1, so this block completed
+            // columns tb + 1 .. tb + KD; flush them 64 at a time
+            if (((tb + KD) & 63) == 0) flush_cols(tb + KD - 63, 64);
+        }
+        // Steps ran for tau = -1 .. tb - 1. Pending: the row of the last step
+        // (its transpose slot is 0 since tb is a multiple of 8) and the columns
+        // completed since the last 64-column flush: (tb & ~63) + 1 .. tb.
+        if (tb & 63) flush_cols((tb & ~63) + 1, tb & 63);
+        flush_rows(i0 + tb, 1);
+        // columns still held by the lanes: slot (tb + 1 + d) % KD = (1 + d) % KD
+        // holds local column tb + 1 + KD lane + d
+#pragma unroll
+        for (int d = 0; d < KD; ++d) {
+            const double v = colacc[(1 + d) % KD];
+            const int64_t j = cb + tb + 1 + (int64_t)KD * lane + d;
+            if (j < N && flushable(KIND, v)) {
+                const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
+                const int64_t i = j - k_lo - (int64_t)(kb & (uint64_t)(WD - 1));
+                atomicMin(&s.keys[j], pack_key(to_minimised(KIND, v), (unsigned long long)i, gmask));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Segments per band and their prefix sums; also resets the work counter.
+// Band b covers diagonals [excl + b W, excl + (b+1) W); its longest diagonal
+// has N - excl - b W rows, split into segments of seg_rows.
+__global__ void __launch_bounds__(1024) k_band_plan(int64_t N, int32_t excl, BandPlan bp)
+{
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int nb = bp.nbands;
+    const int per = (nb + 1023) / 1024;
+    const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+    int64_t sum = 0;
+    for (int b = b0; b < b1; ++b) {
+        int64_t rows = N - excl - (int64_t)b * bp.band_width;
+        sum += (rows + bp.seg_rows - 1) / bp.seg_rows;
+    }
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int64_t run = 0;
+        for (int u = 0; u < 1024; ++u) {
+            int64_t v = part[u];
+            part[u] = run;
+            run += v;
+        }
+        bp.band_start[nb] = run;
+        *bp.next_item = 0u;
+    }
+    __syncthreads();
+    int64_t run = part[t];
+    for (int b = b0; b < b1; ++b) {
+        bp.band_start[b] = run;
+        int64_t rows = N - excl - (int64_t)b * bp.band_width;
+        run += (rows + bp.seg_rows - 1) / bp.seg_rows;
+    }
+}
+
+hipError_t launch_plan(const Series &s, const BandPlan &bp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_band_plan, dim3(1), dim3(1024), 0, st, s.N, s.excl, bp);
+    return hipGetLastError();
+}
+
+template <int KD>
+static hipError_t launch_kd(const Series &s, const BandPlan &bp, int32_t grid, hipStream_t st)
+{
+    if (s.kind == AAMP)
+        hipLaunchKernelGGL((k_sweep_band<AAMP, P_TWO, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+    else if (s.kind == ACAMP)
+        hipLaunchKernelGGL((k_sweep_band<ACAMP, P_TWO, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+    else if (s.pclass == P_ONE)
+        hipLaunchKernelGGL((k_sweep_band<PNORM, P_ONE, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+    else if (s.pclass == P_THREE)
+        hipLaunchKernelGGL((k_sweep_band<PNORM, P_THREE, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_band(const Series &s, const BandPlan &bp, int32_t diags_per_lane,
+                             int32_t grid, hipStream_t st)
+{
+    if (diags_per_lane == 8) return launch_kd<8>(s, bp, grid, st);
+    if (diags_per_lane == 16) return launch_kd<16>(s, bp, grid, st);
+    return hipErrorInvalidValue;
+}
+
+template <int KD>
+static int32_t occupancy_kd(const Series &s)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (s.kind == AAMP)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<AAMP, P_TWO, KD>, 64, 0);
+    else if (s.kind == ACAMP)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<ACAMP, P_TWO, KD>, 64, 0);
+    else if (s.pclass == P_ONE)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_ONE, KD>, 64, 0);
+    else if (s.pclass == P_THREE)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_THREE, KD>, 64, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+int32_t band_blocks_per_cu(const Series &s, int32_t diags_per_lane)
+{
+    return diags_per_lane == 16 ? occupancy_kd<16>(s) : occupancy_kd<8>(s);
+}
+
+int32_t band_lds_bytes(int32_t kind, int32_t diags_per_lane)
+{
+    const int nf = kind == ACAMP ? 3 : 2;
+    return (int32_t)(8 * (nf * 64 * diags_per_lane + NRB * 64 + 64));
+}
+
+}  // namespace mpk

@@ -86,5 +86,13 @@ hipError_t launch_fallback(const Series &s, const Fallback &fb, double *P, int64
                            hipStream_t st);
 
 int32_t band_lds_bytes(int32_t kind, int32_t diags_per_lane);
+int32_t band_blocks_per_cu(const Series &s, int32_t diags_per_lane);
+
+// Band kernels exist for AAMP, ACAMP and p-norm with p in {1, 3}; other p use
+// the simple kernel (the sentinel entries are only sized for those powers).
+inline bool band_supported(const Series &s)
+{
+    return s.kind == AAMP || s.kind == ACAMP || (s.kind == PNORM && (s.pclass == P_ONE || s.pclass == P_THREE));
+}
 
 }  // namespace mpk

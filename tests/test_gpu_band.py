@@ -1,0 +1,135 @@
+"""GPU parity of the band sweep kernel (forced with MP_SWEEP=band) on shapes
+that exercise its edges: partial last bands, segments of one row, the triangle
+corner, exclusion zones of every size, constant runs, exact copies."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.parity import check_profile
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1901_05708_amd as m
+    m.load()
+    return m
+
+
+def _call(mp, kind, T, m, p=2.0, excl=None, R=0, sweep="band", precision="fp64"):
+    import torch
+    old = os.environ.get("MP_SWEEP")
+    os.environ["MP_SWEEP"] = sweep
+    try:
+        Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
+        if kind == "aamp":
+            P, I = mp.aamp(Td, m, excl=excl, R=R, precision=precision)
+        elif kind == "pnorm":
+            P, I = mp.pnorm(Td, m, p=p, excl=excl, R=R, precision=precision)
+        else:
+            P, I = mp.acamp(Td, m, excl=excl, R=R, precision=precision)
+        torch.cuda.synchronize()
+    finally:
+        if old is None:
+            del os.environ["MP_SWEEP"]
+        else:
+            os.environ["MP_SWEEP"] = old
+    return P.cpu().numpy(), I.cpu().numpy()
+
+
+def _check(mp, kind, T, m, p=2.0, excl=None, R=0, label=""):
+    excl = excl or W.excl_default(m)
+    _note(f"{label}: band kind={kind} p={p} n={len(T)} m={m} excl={excl} R={R}")
+    P, I = _call(mp, kind, T, m, p=p, excl=excl, R=R)
+    Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl)
+    atol = 1e-6 if kind == "acamp" else 0.0
+    return check_profile(T, m, kind, p, excl, P, I, Pr, Ir, Qr, 1e-9, atol, label=label), P, I
+
+
+# N - excl relative to the band width 512 (8 diagonals x 64 lanes): below one
+# band, exactly one, one plus a bit, several with a ragged last band
+@pytest.mark.parametrize("n", [400, 560, 600, 1100, 2500])
+@pytest.mark.parametrize("kind", ["aamp", "acamp"])
+def test_band_ragged_sizes(mp, n, kind):
+    rng = np.random.default_rng(n)
+    T = np.cumsum(rng.standard_normal(n))
+    _check(mp, kind, T, 24, label=f"ragged{n}")
+
+
+# segment lengths that leave 1-row and partial-block segments
+@pytest.mark.parametrize("R", [8, 16, 24, 64, 200])
+def test_band_segment_lengths(mp, R):
+    rng = np.random.default_rng(200 + R)
+    T = np.cumsum(rng.standard_normal(1700))
+    _check(mp, "aamp", T, 40, R=R, label=f"R{R}")
+    _check(mp, "acamp", T, 40, R=R, label=f"R{R}z")
+
+
+@pytest.mark.parametrize("excl", [1, 3, 100, 700])
+def test_band_exclusion_zones(mp, excl):
+    rng = np.random.default_rng(300 + excl)
+    T = rng.uniform(-1, 1, 1500)
+    _check(mp, "aamp", T, 16, excl=excl, label=f"excl{excl}")
+
+
+@pytest.mark.parametrize("p", [1.0, 3.0])
+def test_band_pnorm(mp, p):
+    T, _ = W.sines(n=2600, m=32)
+    _check(mp, "pnorm", T, 32, p=p, label=f"pnorm{p}")
+
+
+def test_band_acamp_constant_runs_and_motifs(mp):
+    T, m, planted = W.rw128k(n=5000, m=48, nruns=5, nmotifs=3, run_len=(80, 400))
+    info, P, I = _check(mp, "acamp", T, m, label="runs")
+    for s, L in planted.runs:
+        inside = np.arange(s, s + L - m + 1)
+        assert np.all(np.isinf(P[inside])) and np.all(I[inside] == -1)
+    for a, b in planted.motifs:
+        assert I[a] == b and I[b] == a
+
+
+def test_band_exact_copy_and_zero_keys(mp):
+    rng = np.random.default_rng(17)
+    T = np.cumsum(rng.standard_normal(3000))
+    m, a, b = 64, 100, 1900
+    T[b:b + m] = T[a:a + m]
+    P, I = _call(mp, "aamp", T, m)
+    assert P[a] == 0.0 and P[b] == 0.0 and I[a] == b and I[b] == a
+    T2 = np.full(900, 2.0)
+    P, I = _call(mp, "aamp", T2, 16)
+    assert np.all(P == 0.0)
+    assert np.all(np.abs(np.arange(len(I)) - I) >= W.excl_default(16))
+
+
+def test_band_matches_simple_kernel(mp):
+    T, m = W.rw8k()
+    Pb, Ib = _call(mp, "aamp", T, m, sweep="band")
+    Ps, Is = _call(mp, "aamp", T, m, sweep="simple")
+    same = Ib == Is
+    assert same.mean() > 0.999
+    assert np.array_equal(Pb[same], Ps[same])
+
+
+def test_band_rw8k_full(mp):
+    T, m = W.rw8k()
+    info, _, _ = _check(mp, "aamp", T, m, label="rw8k-band")
+    print(info)
+
+
+def test_band_repeatable(mp):
+    T, m = W.rw8k()
+    P1, I1 = _call(mp, "acamp", T, m)
+    P2, I2 = _call(mp, "acamp", T, m)
+    assert np.array_equal(P1, P2) and np.array_equal(I1, I2)
