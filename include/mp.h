@@ -147,8 +147,8 @@ void mp_release(void);
  * recording. Returns MP_OK, or MP_EINVAL if out is NULL.
  */
 typedef struct mp_stats {
-    double ms_prep;          /* window statistics, difference streams, key fill */
-    double ms_sweep;         /* the diagonal sweep (all its launches)           */
+    double ms_prep;          /* window statistics, difference streams, key fill, work plan */
+    double ms_sweep;         /* the diagonal sweep kernel alone                 */
     double ms_finalize;      /* rescoring, certification and fallback           */
     int64_t pairs;           /* admissible unordered pairs                      */
     int64_t fallback_rows;   /* rows recomputed exactly in FP64                 */

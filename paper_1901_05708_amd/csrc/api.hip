@@ -372,9 +372,9 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
     if ((rc = prof_begin(st, &es, &prof))) return rc;
 
     HIP_TRY(launch_prep(s, st), "prep launch");
+    if (pl.band) HIP_TRY(launch_plan(s, bp, st), "plan launch");
     if (prof) HIP_TRY(hipEventRecord(es.ev[1], st), "hipEventRecord");
     if (pl.band) {
-        HIP_TRY(launch_plan(s, bp, st), "plan launch");
         HIP_TRY(launch_sweep_band(s, bp, pl.diags_per_lane, pl.grid, st), "sweep launch");
     } else {
         HIP_TRY(launch_sweep_simple(s, pl.R, st), "sweep launch");
