@@ -35,8 +35,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--refresh", type=int, default=0, help="refresh interval R (0: library default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: auto)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -101,7 +104,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        return mp.acamp(Td, m, excl=excl, precision=args.precision, stream=stream)
+        return mp.acamp(Td, m, excl=excl, precision=args.precision, R=args.refresh, stream=stream)
 
     for _ in range(args.warmup):
         P, I = step()
@@ -166,6 +169,15 @@ def main():
         },
         "wall_s": round(wall, 3),
     }
+    if args.copy_calib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the ones read for the sweep
+        src = torch.ones(args.copy_calib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = int(src.numel() * 8)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(T, m, excl, kind, P.cpu().numpy(), I.cpu().numpy(),
                                            args.cpu_rows)

@@ -19,7 +19,8 @@ from dataclasses import dataclass
 from typing import Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmp.so")
+# MP_LIBRARY selects another build of the same library (e.g. a debug build).
+LIB_PATH = os.environ.get("MP_LIBRARY") or os.path.join(_HERE, "libmp.so")
 
 MP_OK, MP_EINVAL, MP_ENOMEM, MP_EHIP, MP_EUNSUPPORTED = 0, -1, -2, -3, -4
 MP_FP64, MP_FP32_REFRESH = 0, 1

@@ -256,27 +256,27 @@ int device_cus(int dev)
     return g_dev[dev].cus;
 }
 
-int64_t segments_total(int64_t N, int64_t excl, int64_t W, int64_t R, int64_t *nbands)
+// Rows summed over all bands (band b: N - excl - b W rows) and the band count.
+int64_t band_rows_total(int64_t N, int64_t excl, int64_t W, int64_t *nbands)
 {
     const int64_t nd = N - excl;
     const int64_t nb = (nd + W - 1) / W;
-    int64_t t = 0;
-    for (int64_t b = 0; b < nb; ++b) t += (nd - b * W + R - 1) / R;
     *nbands = nb;
-    return t;
+    // sum_{b < nb} (nd - b W)
+    return nb * nd - W * (nb * (nb - 1) / 2);
 }
 
-// Kernel and shape. The band kernel needs at least one full band; the refresh
-// interval R (rows per segment) defaults to the value that gives every wave
-// slot of the persistent grid a few items, clamped to [256, 4096] rows: the
-// exact restart costs 2m operations per diagonal per segment, and longer
-// segments let FP64 round-off drift further between restarts.
+// Kernel and shape. The band kernel needs at least half a band of diagonals.
+// Its persistent grid gives every wave an equal share of the band-major row
+// space; R bounds the rows between exact FP64 restarts (each restart costs 2m
+// operations per diagonal, and longer runs let round-off drift further).
 int make_plan(const Series &s, int32_t R_user, int dev, Plan *pl)
 {
     const int64_t ndiag = s.N - s.excl;
     Plan p;
     std::string choice = sweep_choice();
-    const int32_t kd = 8;
+    int32_t kd = 8;
+    if (const char *e = std::getenv("MP_KD")) kd = (std::atoi(e) == 16) ? 16 : 8;
     const int64_t W = 64 * kd;
     p.band = band_supported(s) && ndiag >= W / 2 && choice != "simple";
     if (choice == "band" && band_supported(s) && ndiag > 0) p.band = true;
@@ -284,16 +284,13 @@ int make_plan(const Series &s, int32_t R_user, int dev, Plan *pl)
     if (p.band) {
         p.diags_per_lane = kd;
         const int64_t slots = (int64_t)device_cus(dev) * band_blocks_per_cu(s, kd);
-        int64_t R = R_user;
-        if (R <= 0) {
-            const int64_t pairs = pair_count(s.N, s.excl);
-            R = pairs / std::max<int64_t>(1, W * slots * 4);
-            R = std::min<int64_t>(4096, std::max<int64_t>(256, R));
-        }
-        R = ((R + kd - 1) / kd) * kd;   // whole blocks of steps
+        const int64_t rows = band_rows_total(s.N, s.excl, W, &p.nbands);
+        int64_t R = R_user > 0 ? R_user : 4096;
         p.R = (int32_t)std::min<int64_t>(R, INT32_MAX / 2);
-        p.items = segments_total(s.N, s.excl, W, p.R, &p.nbands);
-        p.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(slots, p.items));
+        // at least 64 rows per wave
+        p.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(slots, rows / 64));
+        const int64_t share = (rows + p.grid - 1) / p.grid;
+        p.items = (int64_t)p.grid * ((share + p.R - 1) / p.R) + p.nbands;   // upper bound
     } else {
         int32_t R = R_user > 0 ? R_user : 1024;
         // the simple kernel's grid has one row of blocks per segment
@@ -355,7 +352,6 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
     BandPlan bp;
     std::memset(&bp, 0, sizeof(bp));
     if (pl.band) {
-        if (pl.items >= (int64_t)INT32_MAX) return fail(MP_EINVAL, "series too long for this refresh interval");
         {
             std::lock_guard<std::mutex> lk(g_mu);
             if ((rc = ensure_bands(*w, pl.nbands))) return rc;
@@ -364,7 +360,6 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
         bp.seg_rows = pl.R;
         bp.nbands = (int32_t)pl.nbands;
         bp.band_start = w->band_start;
-        bp.next_item = w->next_item;
     }
 
     EvSet es;

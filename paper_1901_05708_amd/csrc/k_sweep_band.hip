@@ -113,6 +113,33 @@ __device__ __forceinline__ bool flushable(int kind, double v)
     return kind == ACAMP ? (v < 1e300) : (v < 1e190);
 }
 
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
+// DPP wave_shr:1 into the register of `keep`: lane l > 0 receives lane l-1's
+// `hist`, lane 0 keeps `keep`.
+__device__ __forceinline__ double shift_up_keep(double hist, double keep)
+{
+    unsigned long long h = (unsigned long long)__double_as_longlong(hist);
+    unsigned long long k = (unsigned long long)__double_as_longlong(keep);
+    int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)k, (int)(uint32_t)h, 0x138, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(k >> 32), (int)(uint32_t)(h >> 32), 0x138, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// min with a DPP-permuted copy (dpp_ctrl a compile-time constant)
+template <int CTRL>
+__device__ __forceinline__ double fmin_dpp(double v)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    double o = __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+    return fmin_key(v, o);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1;       // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;       // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+
 // Wave-uniform reads go through the constant address space so that they
 // become scalar loads (the data is read-only for the whole launch).
 typedef const __attribute__((address_space(4))) double cdouble;
@@ -138,7 +165,6 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
 
     __shared__ double ring[NF][RING];
     __shared__ double rowbuf[NRB * 64];
-    __shared__ double colout[64];
 
     const int lane = threadIdx.x;
     const int64_t N = s.N;
@@ -152,28 +178,37 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
     for (int d = 0; d < KD; ++d) wd[d] = (uint32_t)(lane * KD + d);
 
     cint64 *band_start = as_const(bp.band_start);
-    const int64_t total = band_start[bp.nbands];
+    const int64_t total = band_start[bp.nbands];   // rows summed over all bands
     cdouble *Tc = as_const(s.T);
     cdouble *xc = as_const(s.x);
     cdouble *yc = as_const(s.y);
     cdouble *zc = as_const(s.z);
 
-    for (;;) {
-        int item = 0;
-        if (lane == 0) item = (int)atomicAdd(bp.next_item, 1u);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if ((int64_t)item >= total) break;
+    // This wave's share of the band-major row space: every row of a band costs
+    // the same (pairs past the series end run on sentinels), so equal row
+    // ranges are equal work. share = total / G rows, the first total % G waves
+    // take one more.
+    const int64_t G = gridDim.x;
+    const int64_t w = blockIdx.x;
+    const int64_t qrows = total / G, rrows = total % G;
+    int64_t pos = uniform64(w * qrows + min(w, rrows));
+    const int64_t pend = uniform64(pos + qrows + (w < rrows ? 1 : 0));
 
-        // band of this item: band_start[b] <= item < band_start[b + 1]
+    while (pos < pend) {
+        // band holding row position pos: band_start[b] <= pos < band_start[b + 1]
         int lo = 0, hi = bp.nbands;
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (band_start[mid] <= item) lo = mid;
+            if (band_start[mid] <= pos) lo = mid;
             else hi = mid;
         }
+        // one item: rows of band lo from pos up to the end of the range, the
+        // band, or the refresh interval, whichever comes first
         const int64_t k_lo = uniform64((int64_t)s.excl + (int64_t)lo * WD);
-        const int64_t i0 = uniform64(((int64_t)item - band_start[lo]) * bp.seg_rows);
-        const int64_t i1 = uniform64(min(i0 + (int64_t)bp.seg_rows, N - k_lo));
+        const int64_t seg = uniform64(min(min(pend, band_start[lo + 1]), pos + (int64_t)bp.seg_rows) - pos);
+        const int64_t i0 = uniform64(pos - band_start[lo]);
+        const int64_t i1 = i0 + seg;
+        pos += seg;
         const int nsteps = (int)(i1 - i0) - 1;      // recurrence steps after the first row
         const int64_t cb = i0 + k_lo;               // stream index of local column 0
 
@@ -222,7 +257,7 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         }
 
         // ---- stage the column streams in the LDS ring: local columns [0, RING)
-        __syncthreads();
+        lds_order();
 #pragma unroll
         for (int q = 0; q < RING / 64; ++q) {
             const int c = lane + 64 * q;
@@ -231,7 +266,7 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
             ring[1][e] = s.y[cb + c];
             if (KIND == ACAMP) ring[2][e] = s.z[cb + c];
         }
-        __syncthreads();
+        lds_order();
 
         // register window of column operands: slot c % KD holds local column c
         // of this lane's window; slots 1..KD-1 are preloaded for tau = 0
@@ -260,58 +295,59 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         // transpose, column minima into the rotating accumulators, then the
         // column whose last diagonal in this lane was d = 0 moves one lane down.
         // The accumulator of diagonal d lives in slot (sbase + d) % KD.
+        double hist = INF;   // lane p: key of the column that left lane 0 p steps ago
         auto reduce_step = [&](int tau, int sbase, const double (&v)[KD]) {
-            double rowmin = INF;
+            double key[KD];
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
-                const double key = make_key(v[d], notmask, wd[d]);
-                rowmin = fmin_key(rowmin, key);
-                colacc[(sbase + d) % KD] = fmin_key(colacc[(sbase + d) % KD], key);
+                key[d] = make_key(v[d], notmask, wd[d]);
+                colacc[(sbase + d) % KD] = fmin_key(colacc[(sbase + d) % KD], key[d]);
             }
-            rowbuf[((tau + 1) & (NRB - 1)) * 64 + lane] = rowmin;
+#pragma unroll
+            for (int w = 1; w < KD; w *= 2)
+#pragma unroll
+                for (int d = 0; d + w < KD; d += 2 * w) key[d] = fmin_key(key[d], key[d + w]);
+            rowbuf[((tau + 1) & (NRB - 1)) * 64 + lane] = key[0];
             const double done = colacc[sbase % KD];
-            if (lane == 0) colout[(tau + 1) & 63] = done;
             colacc[sbase % KD] = shift_down_inf(done);
+            hist = shift_up_keep(hist, done);
         };
 
         // LDS transpose flush of the rows whose slots are 0..cnt-1; slot 0
-        // holds row rbase.
+        // holds row rbase. Lane l reduces row l / 8 over lanes 8 (l % 8) ..
+        // 8 (l % 8) + 7 (8 consecutive doubles), then the 8 lanes of a group
+        // combine with three DPP steps (xor 1, xor 2, half-row mirror).
         auto flush_rows = [&](int64_t rbase, int cnt) {
-            __syncthreads();
-            const int r = lane & (NRB - 1);
-            const int g = lane >> 3;
+            lds_order();
+            const int r = lane >> 3;
             double v = INF;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v = fmin_key(v, rowbuf[r * 64 + g * 8 + q]);
-            v = fmin_key(v, __shfl_xor(v, 8));
-            v = fmin_key(v, __shfl_xor(v, 16));
-            v = fmin_key(v, __shfl_xor(v, 32));
+            for (int q = 0; q < 8; ++q) v = fmin_key(v, rowbuf[lane * 8 + q]);
+            v = fmin_dpp<DPP_QUAD_XOR1>(v);
+            v = fmin_dpp<DPP_QUAD_XOR2>(v);
+            v = fmin_dpp<DPP_ROW_HALF_MIRROR>(v);
             const int64_t row = rbase + r;
-            if (g == 0 && r < cnt && row < i1 && flushable(KIND, v)) {
+            if ((lane & 7) == 0 && r < cnt && row < i1 && flushable(KIND, v)) {
                 const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
                 const int64_t j = row + k_lo + (int64_t)(kb & (uint64_t)(WD - 1));
                 const unsigned long long idx = (j < N) ? (unsigned long long)j : gmask;
                 atomicMin(&s.keys[row], pack_key(to_minimised(KIND, v), idx, gmask));
             }
-            __syncthreads();
+            lds_order();
         };
 
-        // flush the columns that left lane 0; colout entry c % 64 holds local
-        // column c, for the cnt <= 64 columns c0 .. c0 + cnt - 1 (batches are
-        // 1..64, 65..128, ..., so entries never collide before their flush).
-        auto flush_cols = [&](int c0, int cnt) {
-            __syncthreads();
+        // flush columns from the history register: lane p holds local column
+        // cend - p; lanes p < cnt take part.
+        auto flush_cols = [&](int cend, int cnt) {
             if (lane < cnt) {
-                const int c = c0 + lane;
-                const double v = colout[c & 63];
-                const int64_t j = cb + c;
+                const double v = hist;
+                const int64_t j = cb + cend - lane;
                 if (j < N && flushable(KIND, v)) {
                     const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
                     const int64_t i = j - k_lo - (int64_t)(kb & (uint64_t)(WD - 1));
                     atomicMin(&s.keys[j], pack_key(to_minimised(KIND, v), (unsigned long long)i, gmask));
                 }
             }
-            __syncthreads();
         };
 
         // ---- first row (tau = -1): start values only ------------------------
@@ -333,6 +369,20 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         double bx = s.x[cb + RING + bl];
         double by = s.y[cb + RING + bl];
         double bz = (KIND == ACAMP) ? s.z[cb + RING + bl] : 0.0;
+        // the row operands of a block (scalar registers), fetched during the
+        // previous block
+        double rxs[KD], rys[KD], rzs[KD];
+        {
+            cdouble *xr = xc + (i0 + 1);
+            cdouble *yr = yc + (i0 + 1);
+            cdouble *zr = zc + (i0 + 1);
+#pragma unroll
+            for (int q = 0; q < KD; ++q) {
+                rxs[q] = xr[q];
+                rys[q] = yr[q];
+                rzs[q] = (KIND == ACAMP) ? -zr[q] : 0.0;
+            }
+        }
         int tb = 0;
         for (; tb < nsteps; tb += KD) {
             tb = __builtin_amdgcn_readfirstlane(tb);
@@ -341,14 +391,14 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
             cdouble *xr = xc + rb;
             cdouble *yr = yc + rb;
             cdouble *zr = zc + rb;
-            __syncthreads();
+            lds_order();
             if (lane < KD) {
                 const int e = ring_pos<KD>((tb + RING + lane) & (RING - 1));
                 ring[0][e] = bx;
                 ring[1][e] = by;
                 if (KIND == ACAMP) ring[2][e] = bz;
             }
-            __syncthreads();
+            lds_order();
             {
                 const int64_t c = cb + tb + KD + RING + bl;
                 bx = s.x[c];
@@ -368,10 +418,9 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                     cy[q] = ring[1][e];
                     if (KIND == ACAMP) cz[q] = ring[2][e];
                 }
-                const double rx = xr[q];
-                const double ry = yr[q];
-                double rinv = 0.0;
-                if (KIND == ACAMP) rinv = -zr[q];
+                const double rx = rxs[q];
+                const double ry = rys[q];
+                const double rinv = rzs[q];
                 double v[KD];
 #pragma unroll
                 for (int d = 0; d < KD; ++d) {
@@ -389,17 +438,26 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                     }
                 }
                 reduce_step(tau, q + 1, v);
+                if (q == KD - 1) {
+                    // next block's row operands (rows past i1 read padding entries)
+#pragma unroll
+                    for (int u = 0; u < KD; ++u) {
+                        rxs[u] = xr[KD + u];
+                        rys[u] = yr[KD + u];
+                        rzs[u] = (KIND == ACAMP) ? -zr[KD + u] : 0.0;
+                    }
+                }
                 // tb is a multiple of KD and NRB divides KD: (tau + 1) % NRB == (q + 1) % NRB
                 if (((q + 1) & (NRB - 1)) == NRB - 1) flush_rows(i0 + tau + 2 - NRB, NRB);
             }
             // the column of step tau is tau + 1, so this block completed
             // columns tb + 1 .. tb + KD; flush them 64 at a time
-            if (((tb + KD) & 63) == 0) flush_cols(tb + KD - 63, 64);
+            if (((tb + KD) & 63) == 0) flush_cols(tb + KD, 64);
         }
         // Steps ran for tau = -1 .. tb - 1. Pending: the row of the last step
         // (its transpose slot is 0 since tb is a multiple of 8) and the columns
         // completed since the last 64-column flush: (tb & ~63) + 1 .. tb.
-        if (tb & 63) flush_cols((tb & ~63) + 1, tb & 63);
+        if (tb & 63) flush_cols(tb, tb & 63);
         flush_rows(i0 + tb, 1);
         // columns still held by the lanes: slot (tb + 1 + d) % KD = (1 + d) % KD
         // holds local column tb + 1 + KD lane + d
@@ -413,13 +471,12 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                 atomicMin(&s.keys[j], pack_key(to_minimised(KIND, v), (unsigned long long)i, gmask));
             }
         }
-        __syncthreads();
+        lds_order();
     }
 }
 
-// Segments per band and their prefix sums; also resets the work counter.
-// Band b covers diagonals [excl + b W, excl + (b+1) W); its longest diagonal
-// has N - excl - b W rows, split into segments of seg_rows.
+// Prefix sums of the rows of each band. Band b covers diagonals
+// [excl + b W, excl + (b+1) W); its longest diagonal has N - excl - b W rows.
 __global__ void __launch_bounds__(1024) k_band_plan(int64_t N, int32_t excl, BandPlan bp)
 {
     __shared__ int64_t part[1024];
@@ -428,10 +485,7 @@ __global__ void __launch_bounds__(1024) k_band_plan(int64_t N, int32_t excl, Ban
     const int per = (nb + 1023) / 1024;
     const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
     int64_t sum = 0;
-    for (int b = b0; b < b1; ++b) {
-        int64_t rows = N - excl - (int64_t)b * bp.band_width;
-        sum += (rows + bp.seg_rows - 1) / bp.seg_rows;
-    }
+    for (int b = b0; b < b1; ++b) sum += N - excl - (int64_t)b * bp.band_width;
     part[t] = sum;
     __syncthreads();
     if (t == 0) {
@@ -442,14 +496,12 @@ __global__ void __launch_bounds__(1024) k_band_plan(int64_t N, int32_t excl, Ban
             run += v;
         }
         bp.band_start[nb] = run;
-        *bp.next_item = 0u;
     }
     __syncthreads();
     int64_t run = part[t];
     for (int b = b0; b < b1; ++b) {
         bp.band_start[b] = run;
-        int64_t rows = N - excl - (int64_t)b * bp.band_width;
-        run += (rows + bp.seg_rows - 1) / bp.seg_rows;
+        run += N - excl - (int64_t)b * bp.band_width;
     }
 }
 

@@ -67,11 +67,10 @@ struct Fallback {
 // Band-sweep work decomposition (computed on the device by launch_plan).
 struct BandPlan {
     int32_t band_width;    // diagonals per band = 64 lanes x diagonals per lane
-    int32_t seg_rows;      // rows per segment (refresh interval R)
+    int32_t seg_rows;      // longest run of rows between exact restarts (refresh interval R)
     int32_t nbands;
     int32_t pad0;
-    int64_t *band_start;   // nbands + 1 prefix sums of segments per band
-    unsigned int *next_item;   // dynamic work counter (zeroed by the plan kernel)
+    int64_t *band_start;   // nbands + 1 prefix sums of the rows of each band
 };
 
 // --- launch wrappers (return the hipError_t of the launch) -------------------
