@@ -1,0 +1,109 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: the GPU computes the whole profile, the oracle checks sampled rows
+(random rows plus the structurally interesting ones: motifs, constant-run
+boundaries, anomalies)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.parity import check_profile
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1901_05708_amd as m
+    m.load()
+    return m
+
+
+def _gpu(mp, kind, T, m, p=2.0, precision="fp64"):
+    import torch
+    Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
+    if kind == "aamp":
+        P, I = mp.aamp(Td, m, precision=precision)
+    elif kind == "pnorm":
+        P, I = mp.pnorm(Td, m, p=p, precision=precision)
+    else:
+        P, I = mp.acamp(Td, m, precision=precision)
+    torch.cuda.synchronize()
+    return P.cpu().numpy(), I.cpu().numpy()
+
+
+def _sampled(mp, kind, T, m, rows, p=2.0, precision="fp64", label=""):
+    excl = W.excl_default(m)
+    _note(f"{label}: kind={kind} p={p} n={len(T)} m={m} rows={len(rows)} prec={precision}")
+    P, I = _gpu(mp, kind, T, m, p=p, precision=precision)
+    rows = np.unique(np.asarray(rows, dtype=np.int64))
+    Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl, rows=rows)
+    rtol = 1e-9 if precision == "fp64" else 1e-4
+    atol = 1e-6 if kind == "acamp" else 0.0
+    info = check_profile(T, m, kind, p, excl, P[rows], I[rows], Pr, Ir, Qr, rtol, atol,
+                         rows=rows, label=label)
+    return info, P, I
+
+
+def test_rw128k_acamp_fp64_sampled(mp):
+    """The bench workload: constant runs -> +inf rows, motifs found."""
+    T, m, planted = W.rw128k()
+    N = len(T) - m + 1
+    rows = list(W.sample_rows(N, 384, seed=11))
+    for a, b in planted.motifs:
+        rows += [a, b]
+    for s, L in planted.runs:
+        rows += [max(0, s - m), max(0, s - m // 2), s - 1 if s > 0 else 0, s,
+                 min(N - 1, s + L - m), min(N - 1, s + L - m + 1), min(N - 1, s + L - 1)]
+    info, P, I = _sampled(mp, "acamp", T, m, rows, label="rw128k")
+    for s, L in planted.runs:
+        inside = np.arange(s, s + L - m + 1)
+        assert np.all(np.isinf(P[inside])) and np.all(I[inside] == -1)
+    const = np.zeros(N, dtype=bool)
+    for s, L in planted.runs:
+        const[s:s + L - m + 1] = True
+    assert not np.any(const[I[I >= 0]])
+    for a, b in planted.motifs:
+        assert I[a] == b and I[b] == a
+    fin = np.isfinite(P)
+    assert np.all(P[fin] >= 0)
+
+
+def test_rw8k_aamp_full(mp):
+    T, m = W.rw8k()
+    excl = W.excl_default(m)
+    P, I = _gpu(mp, "aamp", T, m)
+    Pr, Ir, Qr = oracle.profile(T, m, "aamp", excl=excl)
+    check_profile(T, m, "aamp", 2.0, excl, P, I, Pr, Ir, Qr, 1e-9, 0.0, label="rw8k")
+
+
+@pytest.mark.parametrize("p", [1.0, 3.0])
+def test_sines_pnorm_sampled(mp, p):
+    T, m = W.sines()
+    N = len(T) - m + 1
+    _sampled(mp, "pnorm", T, m, W.sample_rows(N, 256, seed=int(p)), p=p, label=f"sines-p{p}")
+
+
+@pytest.mark.parametrize("kind", ["acamp", "aamp"])
+def test_ecg_2m_sampled(mp, kind):
+    T, m, anomalies = W.ecg()
+    N = len(T) - m + 1
+    rows = list(W.sample_rows(N, 48, seed=5))
+    for c in anomalies:
+        rows += [max(0, c - m // 2)]
+    _sampled(mp, kind, T, m, rows, label=f"ecg-{kind}")
+
+
+def test_uniform_paper_shape_sampled(mp):
+    T, m = W.uniform()
+    N = len(T) - m + 1
+    _sampled(mp, "acamp", T, m, W.sample_rows(N, 128, seed=6), label="uniform")
