@@ -131,6 +131,7 @@ def main():
     achieved = ops / (sweep_ms * 1e-3) / 1e12
     peak = PEAK_LANE_OPS / 1e12
 
+    fallback = prof["fallback_rows"] / max(1, prof["calls"])
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -149,7 +150,7 @@ def main():
                         "constant runs and 10 planted motif pairs, m=256, excl=64",
             "n": n, "m": m, "excl": excl, "pairs": pairs, "precision": args.precision,
             "refresh_rows": prof["refresh_rows"], "diags_per_lane": prof["diags_per_lane"],
-            "items": prof["items"],
+            "items": prof["items"], "fallback_rows_per_step": fallback,
         },
         "roofline": {
             "bound": "alu",

@@ -48,9 +48,14 @@ int fail_hip(hipError_t e, const char *where)
 struct Workspace {
     int64_t cap = 0;           // stream entries (N + STREAM_PAD) the buffers hold
     double *x = nullptr, *y = nullptr, *z = nullptr;
+    float *xf = nullptr, *yf = nullptr, *zf = nullptr;
     double *mu = nullptr, *invn = nullptr;
     uint8_t *isconst = nullptr;
     unsigned long long *keys = nullptr;
+    unsigned long long *fb_keys = nullptr;
+    double *fb_ub = nullptr;
+    float *fb_pd = nullptr;            // FB_PIVOTS x cap pivot distances
+    int32_t *fb_pivots = nullptr;
     int32_t *fb_rows = nullptr;
     int32_t *counters = nullptr;       // [0] fallback count, [1..] spare
     int64_t band_cap = 0;
@@ -67,10 +72,17 @@ void free_ws(Workspace &w)
     hipFree(w.x);
     hipFree(w.y);
     hipFree(w.z);
+    hipFree(w.xf);
+    hipFree(w.yf);
+    hipFree(w.zf);
     hipFree(w.mu);
     hipFree(w.invn);
     hipFree(w.isconst);
     hipFree(w.keys);
+    hipFree(w.fb_keys);
+    hipFree(w.fb_ub);
+    hipFree(w.fb_pd);
+    hipFree(w.fb_pivots);
     hipFree(w.fb_rows);
     hipFree(w.counters);
     hipFree(w.band_start);
@@ -120,10 +132,16 @@ int ensure_ws(Workspace &w, int64_t N)
     free_ws(w);
     int rc;
     if ((rc = grow(&w.x, cap, "workspace x")) || (rc = grow(&w.y, cap, "workspace y")) ||
-        (rc = grow(&w.z, cap, "workspace z")) || (rc = grow(&w.mu, cap, "workspace mu")) ||
+        (rc = grow(&w.z, cap, "workspace z")) || (rc = grow(&w.xf, cap, "workspace xf")) ||
+        (rc = grow(&w.yf, cap, "workspace yf")) || (rc = grow(&w.zf, cap, "workspace zf")) ||
+        (rc = grow(&w.mu, cap, "workspace mu")) ||
         (rc = grow(&w.invn, cap, "workspace invn")) ||
         (rc = grow(&w.isconst, cap, "workspace const")) ||
         (rc = grow(&w.keys, cap, "workspace keys")) ||
+        (rc = grow(&w.fb_keys, cap, "workspace fallback keys")) ||
+        (rc = grow(&w.fb_ub, cap, "workspace fallback bounds")) ||
+        (rc = grow(&w.fb_pd, (size_t)cap * FB_PIVOTS, "workspace pivot distances")) ||
+        (rc = grow(&w.fb_pivots, 64, "workspace pivots")) ||
         (rc = grow(&w.fb_rows, cap, "workspace fallback")) ||
         (rc = grow(&w.counters, 64, "workspace counters")) ||
         (rc = grow(&w.next_item, 64, "workspace counter"))) {
@@ -152,6 +170,7 @@ int ensure_bands(Workspace &w, int64_t nbands)
 // ---------------------------------------------------------------------------
 struct EvSet {
     hipEvent_t ev[4];
+    int32_t *fb_host = nullptr;   // pinned copy of the call's fallback count
 };
 
 struct Prof {
@@ -168,6 +187,9 @@ int prof_begin(hipStream_t st, EvSet *es, bool *active)
     *active = g_prof.on;
     if (!*active) return MP_OK;
     for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&es->ev[k]), "hipEventCreate");
+    HIP_TRY(hipHostMalloc((void **)&es->fb_host, sizeof(int32_t), hipHostMallocDefault),
+            "hipHostMalloc");
+    *es->fb_host = 0;
     HIP_TRY(hipEventRecord(es->ev[0], st), "hipEventRecord");
     return MP_OK;
 }
@@ -285,13 +307,17 @@ int make_plan(const Series &s, int32_t R_user, int dev, Plan *pl)
         p.diags_per_lane = kd;
         const int64_t slots = (int64_t)device_cus(dev) * band_blocks_per_cu(s, kd);
         const int64_t rows = band_rows_total(s.N, s.excl, W, &p.nbands);
-        int64_t R = R_user > 0 ? R_user : 4096;
+        // default refresh interval: 4096 rows in FP64; 1024 in FP32, where
+        // drift grows 2^29 times faster per step
+        int64_t R = R_user > 0 ? R_user : (s.fp32 ? 1024 : 4096);
         p.R = (int32_t)std::min<int64_t>(R, INT32_MAX / 2);
         // at least 64 rows per wave
         p.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(slots, rows / 64));
         const int64_t share = (rows + p.grid - 1) / p.grid;
         p.items = (int64_t)p.grid * ((share + p.R - 1) / p.R) + p.nbands;   // upper bound
     } else {
+        // the simple kernel is FP64 only; a single-precision request on a
+        // series too small for the band kernel is served exactly in FP64
         int32_t R = R_user > 0 ? R_user : 1024;
         // the simple kernel's grid has one row of blocks per segment
         int64_t minR = (ndiag + 65534) / 65535;
@@ -341,14 +367,29 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
     s.isconst = w->isconst;
     s.keys = w->keys;
     s.fb_count = w->counters;
+    s.xf = w->xf;
+    s.yf = w->yf;
+    s.zf = w->zf;
+    s.fp32 = (precision == MP_FP32_REFRESH) ? 1 : 0;
+    // MP_FORCE_FALLBACK (tests): send every row through the exact search.
+    if (const char *e = std::getenv("MP_FORCE_FALLBACK")) {
+        const int v = std::atoi(e);
+        s.force_fb = (v == 1 || v == 2) ? v : 0;
+    }
 
     Fallback fb;
     fb.count = w->counters;
     fb.rows = w->fb_rows;
+    fb.keys = w->fb_keys;
+    fb.ub = w->fb_ub;
+    fb.pivots = w->fb_pivots;
+    fb.pd = w->fb_pd;
+    fb.pd_stride = w->cap;
     fb.capacity = (int32_t)std::min<int64_t>(N, INT32_MAX);
 
     Plan pl;
     if ((rc = make_plan(s, R, dev, &pl))) return rc;
+    if (!pl.band) s.fp32 = 0;
     BandPlan bp;
     std::memset(&bp, 0, sizeof(bp));
     if (pl.band) {
@@ -378,6 +419,8 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
     HIP_TRY(launch_finalize(s, fb, P, I, st), "finalize launch");
     HIP_TRY(launch_fallback(s, fb, P, I, st), "fallback launch");
     if (prof) {
+        HIP_TRY(hipMemcpyAsync(es.fb_host, fb.count, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                "hipMemcpyAsync");
         HIP_TRY(hipEventRecord(es.ev[3], st), "hipEventRecord");
         mp_stats cfg{};
         cfg.pairs = pair_count(N, excl);
@@ -467,8 +510,10 @@ void mp_release(void)
 void mp_set_profiling(int on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    for (auto &es : g_prof.pending)
+    for (auto &es : g_prof.pending) {
         for (int k = 0; k < 4; ++k) (void)hipEventDestroy(es.ev[k]);
+        (void)hipHostFree(es.fb_host);
+    }
     g_prof.pending.clear();
     g_prof.acc = mp_stats{};
     g_prof.on = on != 0;
@@ -487,7 +532,9 @@ int mp_profile_read(mp_stats *out)
         g_prof.acc.ms_prep += a;
         g_prof.acc.ms_sweep += b;
         g_prof.acc.ms_finalize += c;
+        g_prof.acc.fallback_rows += *es.fb_host;
         for (int k = 0; k < 4; ++k) (void)hipEventDestroy(es.ev[k]);
+        (void)hipHostFree(es.fb_host);
     }
     g_prof.pending.clear();
     *out = g_prof.acc;

@@ -1,9 +1,11 @@
 // k_finalize.hip -- turn the packed keys into the profile (Algorithm 2's final
 // square-root loop, generalised): decode the winning index of every row,
 // recompute that one pair's distance directly in FP64, take the root. Rows
-// whose winner is not a legal candidate (z-normalized: a constant window, or a
-// row whose every candidate is anti-correlated) are queued and recomputed
-// exactly by k_fallback.
+// whose winner is not a legal candidate (z-normalized: a constant window), or
+// whose FP32 key disagrees with the exact value by more than the single-
+// precision sweep allows, are queued and searched again exactly: k_fallback_scan
+// scores, straight from the definition, every column that the triangle
+// inequality over a few pivot windows cannot exclude.
 #include "keys.h"
 #include "mp_internal.h"
 
@@ -68,6 +70,18 @@ __device__ __forceinline__ bool legal_pair(const Series &s, int64_t i, int64_t j
     return true;
 }
 
+// Queue row i for the exact search, seeded with its best known (key, distance).
+__device__ __forceinline__ void enqueue(const Fallback &fb, int64_t i, unsigned long long seed,
+                                        double ub)
+{
+    const int pos = atomicAdd(fb.count, 1);
+    if (pos < fb.capacity) {
+        fb.rows[pos] = (int32_t)i;
+        fb.keys[pos] = seed;
+        fb.ub[pos] = ub;
+    }
+}
+
 template <int KIND, int PC>
 __global__ void k_finalize(Series s, Fallback fb, double *P, int64_t *I)
 {
@@ -82,62 +96,220 @@ __global__ void k_finalize(Series s, Fallback fb, double *P, int64_t *I)
     }
     const int64_t j = (int64_t)(key & mask);
     if (!legal_pair(s, i, j)) {
-        int pos = atomicAdd(fb.count, 1);
-        if (pos < fb.capacity) fb.rows[pos] = (int32_t)i;
+        enqueue(fb, i, KEY_NONE, __longlong_as_double(0x7FF0000000000000ll));
         return;
     }
-    P[i] = root_of<KIND, PC>(exact_sum<KIND, PC>(s, i, j), s.p);
+    const double ex = exact_sum<KIND, PC>(s, i, j);
+    if (s.force_fb) {
+        if (s.force_fb == 1)
+            enqueue(fb, i, pack_key(ex, (unsigned long long)j, mask), root_of<KIND, PC>(ex, s.p));
+        else
+            enqueue(fb, i, KEY_NONE, __longlong_as_double(0x7FF0000000000000ll));
+        return;
+    }
+    if (s.fp32) {
+        // Self-check of the single-precision sweep: the winner's key value is
+        // its FP32 value (up to the 2^-14 of its index tag); a larger gap to
+        // the exact value means FP32 drift on this row, which is then searched
+        // again exactly, starting from this winner. The key holds the
+        // minimised quantity: the sum (AAMP, p-norm) or 1 - rho = DZ^2 / 2m
+        // (ACAMP).
+        const double kv = key_value(key, mask);
+        const double xv = (KIND == ACAMP) ? ex / (2.0 * (double)s.m) : ex;
+        const double pscale = (KIND == PNORM) ? 0.5 * s.p : 1.0;
+        const double tol = FP32_SELF_CHECK * pscale * fabs(xv) +
+                           (KIND == ACAMP ? FP32_SELF_CHECK_ABS_Z : 0.0);
+        // A winner at exact distance 0 is a minimum whatever the drift.
+        if (ex != 0.0 && !(fabs(kv - xv) <= tol)) {
+            enqueue(fb, i, pack_key(ex, (unsigned long long)j, mask), root_of<KIND, PC>(ex, s.p));
+            return;
+        }
+    }
+    P[i] = root_of<KIND, PC>(ex, s.p);
     I[i] = j;
 }
 
-// Exact row minimum for queued rows: one block per row, every admissible
-// legal column summed directly (the brute force of the definition), ties to
-// the smallest index.
-template <int KIND, int PC>
-__global__ void __launch_bounds__(256) k_fallback(Series s, Fallback fb, double *P, int64_t *I)
+// ---------------------------------------------------------------------------
+// Exact search for queued rows.
+//
+// All three distances are metrics (Euclidean, Minkowski p >= 1, Euclidean
+// between z-normalized windows), so for any pivot window c
+//     D(i, j) >= |D(i, c) - D(j, c)|.
+// k_pivot_dist stores D(c, j) for FB_PIVOTS pivots and every window j; a column
+// whose bound exceeds the row's known upper bound (the exact distance of the
+// single-precision winner) can be neither the minimum nor tied with it and is
+// skipped. The remaining columns are compacted per wavefront and scored
+// exactly. Rows without an upper bound (an illegal winner) score every column.
+// ---------------------------------------------------------------------------
+constexpr int FB_WAVE = 64;
+constexpr int FB_ITERS = 64;                       // 64-column steps per work unit
+constexpr int FB_CHUNK = FB_WAVE * FB_ITERS;       // columns per work unit
+constexpr int FB_MAXM = 1024;                      // longer row windows are read from T
+constexpr int FB_UNROLL = 16;
+// Slack of the pruning test: the stored pivot distances are FP64 sums rounded
+// to FP32 (relative error below 2^-24, plus ~m 2^-53 from the sum).
+constexpr double FB_PD_SLACK = 2.5e-7;
+
+// Pivot windows spread evenly over the series; ACAMP skips constant windows
+// (looking up to 4096 windows ahead, else the pivot is left unused).
+__global__ void k_pick_pivots(Series s, Fallback fb)
 {
-    __shared__ double rv[256];
-    __shared__ int64_t rj[256];
-    const int cnt = min(*fb.count, fb.capacity);
-    for (int r = blockIdx.x; r < cnt; r += gridDim.x) {
-        const int64_t i = fb.rows[r];
-        double bv = __longlong_as_double(0x7FF0000000000000ll);
-        int64_t bj = -1;
-        for (int64_t j = threadIdx.x; j < s.N; j += blockDim.x) {
-            if (!legal_pair(s, i, j)) continue;
-            double v = exact_sum<KIND, PC>(s, i, j);
-            if (v < bv) {   // j ascends within a thread: strict '<' keeps the smallest
-                bv = v;
-                bj = j;
+    if (*fb.count == 0) return;
+    const int lane = threadIdx.x;
+    for (int k = 0; k < FB_PIVOTS; ++k) {
+        const int64_t c0 = ((2 * (int64_t)k + 1) * s.N) / (2 * FB_PIVOTS);
+        int64_t found = -1;
+        for (int t = 0; t < 64 && found < 0; ++t) {
+            const int64_t c = (c0 + (int64_t)t * FB_WAVE + lane) % s.N;
+            const bool ok = !(s.kind == ACAMP && s.isconst[c]);
+            const unsigned long long bal = __ballot(ok);
+            if (bal) {
+                const int first = __ffsll((long long)bal) - 1;
+                found = (c0 + (int64_t)t * FB_WAVE + first) % s.N;
             }
         }
-        rv[threadIdx.x] = bv;
-        rj[threadIdx.x] = bj;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                double ov = rv[threadIdx.x + w];
-                int64_t oj = rj[threadIdx.x + w];
-                double mv = rv[threadIdx.x];
-                int64_t mj = rj[threadIdx.x];
-                if (oj >= 0 && (mj < 0 || ov < mv || (ov == mv && oj < mj))) {
-                    rv[threadIdx.x] = ov;
-                    rj[threadIdx.x] = oj;
+        if (lane == 0) fb.pivots[k] = (int32_t)found;
+    }
+}
+
+template <int KIND, int PC>
+__global__ void __launch_bounds__(256) k_pivot_dist(Series s, Fallback fb)
+{
+    if (*fb.count == 0) return;
+    const int k = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= s.N) return;
+    const int32_t c = fb.pivots[k];
+    float d = 0.0f;
+    if (c >= 0) d = (float)root_of<KIND, PC>(exact_sum<KIND, PC>(s, c, j), s.p);
+    fb.pd[(int64_t)k * fb.pd_stride + j] = d;
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+template <int KIND, int PC>
+__global__ void __launch_bounds__(FB_WAVE) k_fallback_scan(Series s, Fallback fb)
+{
+    __shared__ double q[FB_MAXM];
+    __shared__ int32_t queue[2 * FB_WAVE];
+    const int lane = threadIdx.x;
+    const int cnt = min(*fb.count, fb.capacity);
+    const int64_t nch = (s.N + FB_CHUNK - 1) / FB_CHUNK;
+    const int64_t units = (int64_t)cnt * nch;
+    const unsigned long long mask = (1ull << s.gb) - 1ull;
+    const int m = s.m;
+    const bool staged = m <= FB_MAXM;
+    int64_t prev_row = -1;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int r = (int)(u / nch);
+        const int64_t c = u - (int64_t)r * nch;
+        const int64_t i = fb.rows[r];
+        const double thr = fb.ub[r] * (1.0 + 1e-9);
+        const double mi = (KIND == ACAMP) ? s.mu[i] : 0.0;
+        const double ni = (KIND == ACAMP) ? s.invn[i] : 1.0;
+        if (staged && i != prev_row) {
+            __syncthreads();
+            for (int l = lane; l < m; l += FB_WAVE)
+                q[l] = (KIND == ACAMP) ? (s.T[i + l] - mi) * ni : s.T[i + l];
+            __syncthreads();
+            prev_row = i;
+        }
+        unsigned long long best = KEY_NONE;
+        int qn = 0;
+        // Exact score of column j. The column window is read in batches of
+        // FB_UNROLL independent loads so that their latency overlaps.
+        auto score = [&](int64_t j) {
+            const double *b = s.T + j;
+            const double mj = (KIND == ACAMP) ? s.mu[j] : 0.0;
+            const double nj = (KIND == ACAMP) ? s.invn[j] : 1.0;
+            double acc = 0.0;
+            auto term = [&](double a, double bv) {
+                if (KIND == ACAMP) {
+                    const double d = a - (bv - mj) * nj;
+                    acc = fma(d, d, acc);
+                } else if (KIND == AAMP) {
+                    const double d = a - bv;
+                    acc = fma(d, d, acc);
+                } else {
+                    acc += pn_term<PC>(a - bv, s.p);
+                }
+            };
+            auto qa = [&](int l) {
+                if (staged) return q[l];
+                return (KIND == ACAMP) ? (s.T[i + l] - mi) * ni : s.T[i + l];
+            };
+            int l = 0;
+            for (; l + FB_UNROLL <= m; l += FB_UNROLL) {
+                double bb[FB_UNROLL];
+#pragma unroll
+                for (int u = 0; u < FB_UNROLL; ++u) bb[u] = b[l + u];
+#pragma unroll
+                for (int u = 0; u < FB_UNROLL; ++u) term(qa(l + u), bb[u]);
+            }
+            for (; l < m; ++l) term(qa(l), b[l]);
+            if (KIND == ACAMP) acc *= (double)m;
+            const unsigned long long key = pack_key(acc, (unsigned long long)j, mask);
+            best = key < best ? key : best;
+        };
+        for (int it = 0; it < FB_ITERS; ++it) {
+            const int64_t j = c * FB_CHUNK + (int64_t)it * FB_WAVE + lane;
+            bool cand = legal_pair(s, i, j);
+            for (int k = 0; k < FB_PIVOTS; ++k) {
+                if (__ballot(cand) == 0) break;
+                if (fb.pivots[k] < 0) continue;
+                // the row's own pivot distance is uniform across the wavefront
+                const float pa = fb.pd[(int64_t)k * fb.pd_stride + i];
+                if (cand) {
+                    const double a = pa, b = fb.pd[(int64_t)k * fb.pd_stride + j];
+                    const double lb = fabs(a - b) - FB_PD_SLACK * (a + b);
+                    if (lb > thr) cand = false;       // false for NaN bounds: kept
                 }
             }
+            const unsigned long long bal = __ballot(cand);
+            if (cand) queue[qn + lanes_below(bal)] = (int32_t)j;
+            qn += __popcll(bal);
             __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const int64_t j = rj[0];
-            if (j < 0) {
-                P[i] = __longlong_as_double(0x7FF0000000000000ll);
-                I[i] = -1;
-            } else {
-                P[i] = root_of<KIND, PC>(rv[0], s.p);
-                I[i] = j;
+            if (qn >= FB_WAVE) {
+                score(queue[lane]);
+                const int rest = qn - FB_WAVE;
+                const int32_t moved = lane < rest ? queue[FB_WAVE + lane] : 0;
+                __syncthreads();
+                if (lane < rest) queue[lane] = moved;
+                qn = rest;
+                __syncthreads();
             }
         }
+        if (lane < qn) score(queue[lane]);
         __syncthreads();
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(best, off);
+            best = o < best ? o : best;
+        }
+        if (lane == 0 && best != KEY_NONE) atomicMin(&fb.keys[r], best);
+    }
+}
+
+// Rows of the fallback queue: decode the exact search's winner and rescore it.
+template <int KIND, int PC>
+__global__ void k_fallback_finish(Series s, Fallback fb, double *P, int64_t *I)
+{
+    const int cnt = min(*fb.count, fb.capacity);
+    const unsigned long long mask = (1ull << s.gb) - 1ull;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < cnt; r += gridDim.x * blockDim.x) {
+        const int64_t i = fb.rows[r];
+        const unsigned long long key = fb.keys[r];
+        if (key == KEY_NONE) {
+            P[i] = __longlong_as_double(0x7FF0000000000000ll);
+            I[i] = -1;
+        } else {
+            const int64_t j = (int64_t)(key & mask);
+            P[i] = root_of<KIND, PC>(exact_sum<KIND, PC>(s, i, j), s.p);
+            I[i] = j;
+        }
     }
 }
 
@@ -162,17 +334,21 @@ hipError_t launch_finalize(const Series &s, const Fallback &fb, double *P, int64
 hipError_t launch_fallback(const Series &s, const Fallback &fb, double *P, int64_t *I,
                            hipStream_t st)
 {
-    dim3 g(256), b(256);
-    if (s.kind == AAMP)
-        hipLaunchKernelGGL((k_fallback<AAMP, P_TWO>), g, b, 0, st, s, fb, P, I);
-    else if (s.kind == ACAMP)
-        hipLaunchKernelGGL((k_fallback<ACAMP, P_TWO>), g, b, 0, st, s, fb, P, I);
-    else if (s.pclass == P_ONE)
-        hipLaunchKernelGGL((k_fallback<PNORM, P_ONE>), g, b, 0, st, s, fb, P, I);
-    else if (s.pclass == P_THREE)
-        hipLaunchKernelGGL((k_fallback<PNORM, P_THREE>), g, b, 0, st, s, fb, P, I);
-    else
-        hipLaunchKernelGGL((k_fallback<PNORM, P_GENERIC>), g, b, 0, st, s, fb, P, I);
+    // Every kernel returns at once when the queue is empty.
+    const dim3 gpd((unsigned)((s.N + 255) / 256), FB_PIVOTS);
+    hipLaunchKernelGGL(k_pick_pivots, dim3(1), dim3(FB_WAVE), 0, st, s, fb);
+#define MP_FB(K, PCL)                                                                   \
+    do {                                                                                \
+        hipLaunchKernelGGL((k_pivot_dist<K, PCL>), gpd, dim3(256), 0, st, s, fb);         \
+        hipLaunchKernelGGL((k_fallback_scan<K, PCL>), dim3(8192), dim3(FB_WAVE), 0, st, s, fb); \
+        hipLaunchKernelGGL((k_fallback_finish<K, PCL>), dim3(64), dim3(256), 0, st, s, fb, P, I); \
+    } while (0)
+    if (s.kind == AAMP) MP_FB(AAMP, P_TWO);
+    else if (s.kind == ACAMP) MP_FB(ACAMP, P_TWO);
+    else if (s.pclass == P_ONE) MP_FB(PNORM, P_ONE);
+    else if (s.pclass == P_THREE) MP_FB(PNORM, P_THREE);
+    else MP_FB(PNORM, P_GENERIC);
+#undef MP_FB
     return hipGetLastError();
 }
 

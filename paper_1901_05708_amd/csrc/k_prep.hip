@@ -87,6 +87,41 @@ __global__ void k_streams(Series s)
     s.x[j] = x;
     s.y[j] = y;
     if (s.kind == ACAMP) s.z[j] = z;
+    if (s.fp32) {
+        // FP32 copies for the single-precision sweep. Values are recentred by
+        // c = t_0 before rounding (the recurrence only uses differences of
+        // like entries, so the shift cancels), keeping the rounding error
+        // relative to the series' spread rather than its offset.
+        const double c = s.T[0];
+        float xf, yf, zf = (float)z;
+        if (j >= s.N) {
+            if (s.kind == AAMP) {
+                xf = SENTF_EUCLID;
+                yf = SENTF_EUCLID;
+            } else if (s.kind == PNORM) {
+                xf = (s.pclass == P_ONE) ? SENTF_P1 : (s.pclass == P_THREE ? SENTF_P3 : 0.0f);
+                yf = 0.0f;
+            } else {
+                xf = 0.0f;
+                yf = 0.0f;
+            }
+        } else if (j == 0) {
+            xf = 0.0f;
+            yf = 0.0f;
+        } else if (s.kind == AAMP) {
+            xf = (float)x;
+            yf = (float)(y - 2.0 * c);
+        } else if (s.kind == PNORM) {
+            xf = (float)(x - c);
+            yf = (float)(y - c);
+        } else {
+            xf = (float)x;
+            yf = (float)y;
+        }
+        s.xf[j] = xf;
+        s.yf[j] = yf;
+        if (s.kind == ACAMP) s.zf[j] = zf;
+    }
 }
 
 hipError_t launch_prep(const Series &s, hipStream_t st)

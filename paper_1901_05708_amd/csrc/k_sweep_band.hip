@@ -6,27 +6,29 @@
 // minimum of its row i and of its column j. How it is laid out here:
 //
 //  * A work item is a band of 64*KD consecutive diagonals [k_lo, k_lo + 64 KD)
-//    times a segment of rows [i0, i1). One wavefront owns one item at a time
-//    (persistent grid, items taken from an atomic counter).
+//    times a run of rows [i0, i1). One wavefront owns one item at a time; each
+//    wave of the persistent grid owns an equal share of the band-major rows.
 //  * Lane l owns the KD diagonals k_lo + KD l + d. All 64 lanes step through
 //    the rows together, so the row operands are wave-uniform (scalar loads) and
 //    the column operands of a step are KD-strided in the column stream.
 //  * Each item starts with the exact FP64 sums of its first row (the refresh),
-//    then runs the O(1) recurrence for the remaining rows.
+//    then runs the O(1) recurrence for the remaining rows, in the precision F:
+//    double, or float with the start values rounded from the FP64 sums.
 //  * Column operands come from an LDS ring: the stream entries of the item's
 //    columns are staged once (coalesced, one block of KD entries per KD steps,
 //    fetched a block ahead) and each step every lane reads the one entry that
 //    enters its register window of KD columns.
-//  * Minima are kept as packed keys: the double being minimised with its low
+//  * Minima are kept as packed keys: the value being minimised (F) with its low
 //    log2(64 KD) mantissa bits replaced by the wave-local diagonal index, so one
-//    v_min_f64 keeps value and argument together.
+//    min instruction keeps value and argument together.
 //    - row i: min over the lane's KD diagonals in registers, then across the
-//      64 lanes through a small LDS transpose every 8 rows, then one global
-//      atomicMin per row and item;
+//      64 lanes through a small LDS transpose every 8 rows (DPP inside groups
+//      of 8 lanes), then one global atomicMin per row and item;
 //    - column j: the lane keeps a rotating accumulator per column of its
 //      window; after a column's last diagonal in lane l it moves to lane l-1
-//      (one DPP wave shift per step) and when it leaves lane 0 it is complete
-//      for the item and goes to the global keys with one atomicMin.
+//      (one DPP wave shift per step); the column leaving lane 0 enters a
+//      history register (one DPP shift per step) that is flushed with one
+//      global atomicMin per column and item every 64 steps.
 //  * Pairs past the end of the series read sentinel stream entries (see
 //    k_prep) and lose every comparison; rows and columns outside the item or
 //    the series are never written.
@@ -70,81 +72,127 @@ __device__ __forceinline__ int ring_pos(int c)
     return c ^ gxor<KD>(c >> Log2<KD>::v);
 }
 
-__device__ __forceinline__ double fmin_key(double a, double b) { return __builtin_fmin(a, b); }
-
-// Replace the low index bits of a key (double bits) by w.
-__device__ __forceinline__ double make_key(double v, uint32_t notmask, uint32_t w)
-{
-    unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    uint32_t lo = ((uint32_t)b & notmask) | w;
-    uint32_t hi = (uint32_t)(b >> 32);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// DPP wave_shl:1 -- lane l receives lane l+1's key; lane 63 receives +inf
-// (high word 0x7FF00000 kept from `old`, low word zero-filled by bound_ctrl).
-__device__ __forceinline__ double shift_down_inf(double v)
-{
-    unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x130, 0xF, 0xF, true);
-    int hi = __builtin_amdgcn_update_dpp((int)0x7FF00000, (int)(uint32_t)(b >> 32), 0x130, 0xF, 0xF,
-                                         false);
-    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
-}
-
-template <int PC>
-__device__ __forceinline__ double pw(double d)
-{
-    double a = fabs(d);
-    if (PC == P_ONE) return a;
-    return a * a * a;  // P_THREE
-}
-
-__device__ __forceinline__ double to_minimised(int kind, double v)
-{
-    // AAMP / p-norm minimise the pre-root sum itself; ACAMP keys hold -rho and
-    // the global key holds 1 - rho = DZ^2 / 2m (Lemma 3).
-    return kind == ACAMP ? 1.0 + v : v;
-}
-
-__device__ __forceinline__ bool flushable(int kind, double v)
-{
-    // untouched accumulators (+inf) and sentinel sums never reach the keys
-    return kind == ACAMP ? (v < 1e300) : (v < 1e190);
-}
-
-__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
-
-// DPP wave_shr:1 into the register of `keep`: lane l > 0 receives lane l-1's
-// `hist`, lane 0 keeps `keep`.
-__device__ __forceinline__ double shift_up_keep(double hist, double keep)
-{
-    unsigned long long h = (unsigned long long)__double_as_longlong(hist);
-    unsigned long long k = (unsigned long long)__double_as_longlong(keep);
-    int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)k, (int)(uint32_t)h, 0x138, 0xF, 0xF, false);
-    int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(k >> 32), (int)(uint32_t)(h >> 32), 0x138, 0xF, 0xF, false);
-    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
-}
-
-// min with a DPP-permuted copy (dpp_ctrl a compile-time constant)
-template <int CTRL>
-__device__ __forceinline__ double fmin_dpp(double v)
-{
-    unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-    int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
-    double o = __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
-    return fmin_key(v, o);
-}
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
 constexpr int DPP_QUAD_XOR1 = 0xB1;       // quad_perm [1,0,3,2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;       // quad_perm [2,3,0,1]
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;
 
+// --- per-precision key operations -------------------------------------------
+// A key is a value of type F whose low mantissa bits carry an index. Keys are
+// compared with the plain float min instruction (IEEE mode is off for this
+// file; keys are never NaN).
+template <typename F>
+struct Prec;
+
+template <>
+struct Prec<double> {
+    __device__ static double inf() { return __longlong_as_double(0x7FF0000000000000ll); }
+    __device__ static double key(double v, uint32_t notmask, uint32_t w)
+    {
+        unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        uint32_t lo = ((uint32_t)b & notmask) | w;
+        return __longlong_as_double((long long)((b & 0xFFFFFFFF00000000ull) | lo));
+    }
+    __device__ static uint32_t index(double k)
+    {
+        return (uint32_t)(unsigned long long)__double_as_longlong(k);
+    }
+    __device__ static double kmin(double a, double b) { return __builtin_fmin(a, b); }
+    template <int CTRL>
+    __device__ static double dpp(double v)
+    {
+        unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+        int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+        return __longlong_as_double(
+            (long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+    }
+    // wave_shl:1, lane 63 receives +inf (high word from `old`, low word zero)
+    __device__ static double shift_down_inf(double v)
+    {
+        unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, DPP_WAVE_SHL1, 0xF, 0xF, true);
+        int hi = __builtin_amdgcn_update_dpp((int)0x7FF00000, (int)(uint32_t)(b >> 32),
+                                             DPP_WAVE_SHL1, 0xF, 0xF, false);
+        return __longlong_as_double(
+            (long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+    }
+    // wave_shr:1 into the register of `keep`: lane l > 0 receives lane l-1's
+    // `hist`, lane 0 keeps `keep`
+    __device__ static double shift_up_keep(double hist, double keep)
+    {
+        unsigned long long h = (unsigned long long)__double_as_longlong(hist);
+        unsigned long long k = (unsigned long long)__double_as_longlong(keep);
+        int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)k, (int)(uint32_t)h, DPP_WAVE_SHR1,
+                                             0xF, 0xF, false);
+        int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(k >> 32), (int)(uint32_t)(h >> 32),
+                                             DPP_WAVE_SHR1, 0xF, 0xF, false);
+        return __longlong_as_double(
+            (long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+    }
+    // refresh value of a diagonal already past the end (AAMP / p-norm)
+    __device__ static double sentinel() { return SENT_INIT; }
+    __device__ static bool flushable(int kind, double v)
+    {
+        return kind == ACAMP ? (v < 1e300) : (v < 1e190);
+    }
+};
+
+template <>
+struct Prec<float> {
+    __device__ static float inf() { return __int_as_float(0x7F800000); }
+    __device__ static float key(float v, uint32_t notmask, uint32_t w)
+    {
+        return __uint_as_float((__float_as_uint(v) & notmask) | w);
+    }
+    __device__ static uint32_t index(float k) { return __float_as_uint(k); }
+    __device__ static float kmin(float a, float b) { return __builtin_fminf(a, b); }
+    template <int CTRL>
+    __device__ static float dpp(float v)
+    {
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+    }
+    __device__ static float shift_down_inf(float v)
+    {
+        return __int_as_float(__builtin_amdgcn_update_dpp((int)0x7F800000, __float_as_int(v),
+                                                          DPP_WAVE_SHL1, 0xF, 0xF, false));
+    }
+    __device__ static float shift_up_keep(float hist, float keep)
+    {
+        return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(keep), __float_as_int(hist),
+                                                          DPP_WAVE_SHR1, 0xF, 0xF, false));
+    }
+    // refresh value of a diagonal already past the end: +inf (the float
+    // sentinel increments are positive, so it stays +inf)
+    __device__ static float sentinel() { return __int_as_float(0x7F800000); }
+    __device__ static bool flushable(int kind, float v)
+    {
+        (void)kind;
+        return v < 1e30f;
+    }
+};
+
+template <int PC, typename F>
+__device__ __forceinline__ F pw(F d)
+{
+    F a = fabs(d);
+    if (PC == P_ONE) return a;
+    return a * a * a;  // P_THREE
+}
+
+// A workgroup is a single wavefront and LDS executes one wave's accesses in
+// issue order, so ordering LDS accesses only needs the compiler not to move
+// them; no s_waitcnt drain or s_barrier.
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
+
 // Wave-uniform reads go through the constant address space so that they
 // become scalar loads (the data is read-only for the whole launch).
 typedef const __attribute__((address_space(4))) double cdouble;
+typedef const __attribute__((address_space(4))) float cfloat;
 typedef const __attribute__((address_space(4))) int64_t cint64;
 __device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)p; }
+__device__ __forceinline__ cfloat *as_const(const float *p) { return (cfloat *)p; }
 __device__ __forceinline__ cint64 *as_const(const int64_t *p) { return (cint64 *)p; }
 
 __device__ __forceinline__ int64_t uniform64(int64_t v)
@@ -154,35 +202,54 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+template <typename F>
+struct Streams;
+template <>
+struct Streams<double> {
+    __device__ static const double *x(const Series &s) { return s.x; }
+    __device__ static const double *y(const Series &s) { return s.y; }
+    __device__ static const double *z(const Series &s) { return s.z; }
+};
+template <>
+struct Streams<float> {
+    __device__ static const float *x(const Series &s) { return s.xf; }
+    __device__ static const float *y(const Series &s) { return s.yf; }
+    __device__ static const float *z(const Series &s) { return s.zf; }
+};
+
 }  // namespace
 
-template <int KIND, int PC, int KD>
+template <int KIND, int PC, int KD, typename F>
 __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
 {
+    typedef Prec<F> P;
     constexpr int WD = 64 * KD;          // diagonals per item
     constexpr int RING = WD;             // ring entries per field
     constexpr int NF = (KIND == ACAMP) ? 3 : 2;
 
-    __shared__ double ring[NF][RING];
-    __shared__ double rowbuf[NRB * 64];
+    __shared__ F ring[NF][RING];
+    __shared__ F rowbuf[NRB * 64];
 
     const int lane = threadIdx.x;
     const int64_t N = s.N;
     const uint32_t notmask = ~(uint32_t)(WD - 1);
     const unsigned long long gmask = (1ull << s.gb) - 1ull;
-    const double INF = __longlong_as_double(0x7FF0000000000000ll);
+    const F INF = P::inf();
     const int m = s.m;
 
     uint32_t wd[KD];
 #pragma unroll
     for (int d = 0; d < KD; ++d) wd[d] = (uint32_t)(lane * KD + d);
 
+    const F *sx = Streams<F>::x(s);
+    const F *sy = Streams<F>::y(s);
+    const F *sz = Streams<F>::z(s);
     cint64 *band_start = as_const(bp.band_start);
     const int64_t total = band_start[bp.nbands];   // rows summed over all bands
     cdouble *Tc = as_const(s.T);
-    cdouble *xc = as_const(s.x);
-    cdouble *yc = as_const(s.y);
-    cdouble *zc = as_const(s.z);
+    const auto xc = as_const(sx);
+    const auto yc = as_const(sy);
+    const auto zc = as_const(sz);
 
     // This wave's share of the band-major row space: every row of a band costs
     // the same (pairs past the series end run on sentinels), so equal row
@@ -213,7 +280,7 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         const int64_t cb = i0 + k_lo;               // stream index of local column 0
 
         // ---- exact FP64 start values of the first row (the refresh) ----------
-        double S[KD];
+        F S[KD];
         {
             const int64_t jb = cb + (int64_t)KD * lane;   // this lane's first column
             const int64_t tmax = s.n - 1;
@@ -236,14 +303,14 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                         const double tr = Tc[i0 + l];
 #pragma unroll
                         for (int d = 0; d < KD; ++d) {
-                            const double w = win[(q + d) % KD];
+                            const double wv = win[(q + d) % KD];
                             if (KIND == AAMP) {
-                                const double e = tr - w;
+                                const double e = tr - wv;
                                 acc[d] = fma(e, e, acc[d]);
                             } else if (KIND == PNORM) {
-                                acc[d] += pw<PC>(tr - w);
+                                acc[d] += pw<PC, double>(tr - wv);
                             } else {
-                                acc[d] = fma(tr - mui, w - muj[d], acc[d]);
+                                acc[d] = fma(tr - mui, wv - muj[d], acc[d]);
                             }
                         }
                     }
@@ -252,7 +319,7 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
                 const bool valid = (jb + d) <= N - 1;
-                S[d] = valid ? acc[d] : (KIND == ACAMP ? 0.0 : SENT_INIT);
+                S[d] = valid ? (F)acc[d] : (KIND == ACAMP ? (F)0 : P::sentinel());
             }
         }
 
@@ -262,20 +329,20 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         for (int q = 0; q < RING / 64; ++q) {
             const int c = lane + 64 * q;
             const int e = ring_pos<KD>(c);
-            ring[0][e] = s.x[cb + c];
-            ring[1][e] = s.y[cb + c];
-            if (KIND == ACAMP) ring[2][e] = s.z[cb + c];
+            ring[0][e] = sx[cb + c];
+            ring[1][e] = sy[cb + c];
+            if (KIND == ACAMP) ring[2][e] = sz[cb + c];
         }
         lds_order();
 
         // register window of column operands: slot c % KD holds local column c
         // of this lane's window; slots 1..KD-1 are preloaded for tau = 0
-        double cx[KD], cy[KD], cz[KD];
+        F cx[KD], cy[KD], cz[KD];
 #pragma unroll
         for (int d = 0; d < KD; ++d) {
-            cx[d] = 0.0;
-            cy[d] = 0.0;
-            cz[d] = 0.0;
+            cx[d] = (F)0;
+            cy[d] = (F)0;
+            cz[d] = (F)0;
         }
 #pragma unroll
         for (int d = 0; d < KD - 1; ++d) {
@@ -286,52 +353,52 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
             if (KIND == ACAMP) cz[(1 + d) % KD] = ring[2][e];
         }
 
-        double colacc[KD];
+        F colacc[KD];
 #pragma unroll
         for (int d = 0; d < KD; ++d) colacc[d] = INF;
+        F hist = INF;   // lane p: key of the column that left lane 0 p steps ago
 
         // -------------------------------------------------------------------
         // one step: keys of the current values, row minimum into the LDS
         // transpose, column minima into the rotating accumulators, then the
-        // column whose last diagonal in this lane was d = 0 moves one lane down.
+        // column whose last diagonal in this lane was d = 0 moves one lane
+        // down and lane 0's enters the history register.
         // The accumulator of diagonal d lives in slot (sbase + d) % KD.
-        double hist = INF;   // lane p: key of the column that left lane 0 p steps ago
-        auto reduce_step = [&](int tau, int sbase, const double (&v)[KD]) {
-            double key[KD];
+        auto reduce_step = [&](int tau, int sbase, const F (&v)[KD]) {
+            F key[KD];
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
-                key[d] = make_key(v[d], notmask, wd[d]);
-                colacc[(sbase + d) % KD] = fmin_key(colacc[(sbase + d) % KD], key[d]);
+                key[d] = P::key(v[d], notmask, wd[d]);
+                colacc[(sbase + d) % KD] = P::kmin(colacc[(sbase + d) % KD], key[d]);
             }
 #pragma unroll
-            for (int w = 1; w < KD; w *= 2)
+            for (int ww = 1; ww < KD; ww *= 2)
 #pragma unroll
-                for (int d = 0; d + w < KD; d += 2 * w) key[d] = fmin_key(key[d], key[d + w]);
+                for (int d = 0; d + ww < KD; d += 2 * ww) key[d] = P::kmin(key[d], key[d + ww]);
             rowbuf[((tau + 1) & (NRB - 1)) * 64 + lane] = key[0];
-            const double done = colacc[sbase % KD];
-            colacc[sbase % KD] = shift_down_inf(done);
-            hist = shift_up_keep(hist, done);
+            const F done = colacc[sbase % KD];
+            colacc[sbase % KD] = P::shift_down_inf(done);
+            hist = P::shift_up_keep(hist, done);
         };
 
         // LDS transpose flush of the rows whose slots are 0..cnt-1; slot 0
         // holds row rbase. Lane l reduces row l / 8 over lanes 8 (l % 8) ..
-        // 8 (l % 8) + 7 (8 consecutive doubles), then the 8 lanes of a group
-        // combine with three DPP steps (xor 1, xor 2, half-row mirror).
+        // 8 (l % 8) + 7, then the 8 lanes of a group combine with three DPP
+        // steps (xor 1, xor 2, half-row mirror).
         auto flush_rows = [&](int64_t rbase, int cnt) {
             lds_order();
             const int r = lane >> 3;
-            double v = INF;
+            F v = INF;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v = fmin_key(v, rowbuf[lane * 8 + q]);
-            v = fmin_dpp<DPP_QUAD_XOR1>(v);
-            v = fmin_dpp<DPP_QUAD_XOR2>(v);
-            v = fmin_dpp<DPP_ROW_HALF_MIRROR>(v);
+            for (int q = 0; q < 8; ++q) v = P::kmin(v, rowbuf[lane * 8 + q]);
+            v = P::kmin(v, P::template dpp<DPP_QUAD_XOR1>(v));
+            v = P::kmin(v, P::template dpp<DPP_QUAD_XOR2>(v));
+            v = P::kmin(v, P::template dpp<DPP_ROW_HALF_MIRROR>(v));
             const int64_t row = rbase + r;
-            if ((lane & 7) == 0 && r < cnt && row < i1 && flushable(KIND, v)) {
-                const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
-                const int64_t j = row + k_lo + (int64_t)(kb & (uint64_t)(WD - 1));
+            if ((lane & 7) == 0 && r < cnt && row < i1 && P::flushable(KIND, v)) {
+                const int64_t j = row + k_lo + (int64_t)(P::index(v) & (uint32_t)(WD - 1));
                 const unsigned long long idx = (j < N) ? (unsigned long long)j : gmask;
-                atomicMin(&s.keys[row], pack_key(to_minimised(KIND, v), idx, gmask));
+                atomicMin(&s.keys[row], pack_key((double)v, idx, gmask));
             }
             lds_order();
         };
@@ -340,24 +407,23 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         // cend - p; lanes p < cnt take part.
         auto flush_cols = [&](int cend, int cnt) {
             if (lane < cnt) {
-                const double v = hist;
+                const F v = hist;
                 const int64_t j = cb + cend - lane;
-                if (j < N && flushable(KIND, v)) {
-                    const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
-                    const int64_t i = j - k_lo - (int64_t)(kb & (uint64_t)(WD - 1));
-                    atomicMin(&s.keys[j], pack_key(to_minimised(KIND, v), (unsigned long long)i, gmask));
+                if (j < N && P::flushable(KIND, v)) {
+                    const int64_t i = j - k_lo - (int64_t)(P::index(v) & (uint32_t)(WD - 1));
+                    atomicMin(&s.keys[j], pack_key((double)v, (unsigned long long)i, gmask));
                 }
             }
         };
 
         // ---- first row (tau = -1): start values only ------------------------
         {
-            double v[KD];
-            const double rinv0 = (KIND == ACAMP) ? -zc[i0] : 0.0;
+            F v[KD];
+            const F rinv0 = (KIND == ACAMP) ? -zc[i0] : (F)0;
             const int64_t jb = cb + (int64_t)KD * lane;
 #pragma unroll
             for (int d = 0; d < KD; ++d)
-                v[d] = (KIND == ACAMP) ? S[d] * rinv0 * s.z[jb + d] : S[d];
+                v[d] = (KIND == ACAMP) ? fma(S[d] * rinv0, sz[jb + d], (F)1) : S[d];
             reduce_step(-1, 0, v);
         }
         flush_cols(0, 1);   // column 0 has only the first row's pair
@@ -366,21 +432,21 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         // Block tb needs local columns [tb + RING, tb + RING + KD) in the ring;
         // lanes < KD fetch each block one block ahead.
         const int bl = min(lane, KD - 1);
-        double bx = s.x[cb + RING + bl];
-        double by = s.y[cb + RING + bl];
-        double bz = (KIND == ACAMP) ? s.z[cb + RING + bl] : 0.0;
+        F bx = sx[cb + RING + bl];
+        F by = sy[cb + RING + bl];
+        F bz = (KIND == ACAMP) ? sz[cb + RING + bl] : (F)0;
         // the row operands of a block (scalar registers), fetched during the
         // previous block
-        double rxs[KD], rys[KD], rzs[KD];
+        F rxs[KD], rys[KD], rzs[KD];
         {
-            cdouble *xr = xc + (i0 + 1);
-            cdouble *yr = yc + (i0 + 1);
-            cdouble *zr = zc + (i0 + 1);
+            const auto xr = xc + (i0 + 1);
+            const auto yr = yc + (i0 + 1);
+            const auto zr = zc + (i0 + 1);
 #pragma unroll
             for (int q = 0; q < KD; ++q) {
                 rxs[q] = xr[q];
                 rys[q] = yr[q];
-                rzs[q] = (KIND == ACAMP) ? -zr[q] : 0.0;
+                rzs[q] = (KIND == ACAMP) ? -zr[q] : (F)0;
             }
         }
         int tb = 0;
@@ -388,9 +454,9 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
             tb = __builtin_amdgcn_readfirstlane(tb);
             // row operands of this block: rows i0 + 1 + tb + q, q < KD
             const int64_t rb = uniform64(i0 + 1 + tb);
-            cdouble *xr = xc + rb;
-            cdouble *yr = yc + rb;
-            cdouble *zr = zc + rb;
+            const auto xr = xc + rb;
+            const auto yr = yc + rb;
+            const auto zr = zc + rb;
             lds_order();
             if (lane < KD) {
                 const int e = ring_pos<KD>((tb + RING + lane) & (RING - 1));
@@ -401,9 +467,9 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
             lds_order();
             {
                 const int64_t c = cb + tb + KD + RING + bl;
-                bx = s.x[c];
-                by = s.y[c];
-                if (KIND == ACAMP) bz = s.z[c];
+                bx = sx[c];
+                by = sy[c];
+                if (KIND == ACAMP) bz = sz[c];
             }
             // this block's entering columns are tb + KD (lane + 1) + q, all in
             // the aligned column block u = tb / KD + lane + 1
@@ -418,10 +484,10 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                     cy[q] = ring[1][e];
                     if (KIND == ACAMP) cz[q] = ring[2][e];
                 }
-                const double rx = rxs[q];
-                const double ry = rys[q];
-                const double rinv = rzs[q];
-                double v[KD];
+                const F rx = rxs[q];
+                const F ry = rys[q];
+                const F rinv = rzs[q];
+                F v[KD];
 #pragma unroll
                 for (int d = 0; d < KD; ++d) {
                     const int sl = (q + 1 + d) % KD;
@@ -429,12 +495,13 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                         S[d] = fma(rx - cx[sl], ry - cy[sl], S[d]);
                         v[d] = S[d];
                     } else if (KIND == PNORM) {
-                        S[d] += pw<PC>(rx - cx[sl]) - pw<PC>(ry - cy[sl]);
+                        S[d] += pw<PC, F>(rx - cx[sl]) - pw<PC, F>(ry - cy[sl]);
                         v[d] = S[d];
                     } else {
                         S[d] = fma(rx, cy[sl], S[d]);
                         S[d] = fma(cx[sl], ry, S[d]);
-                        v[d] = S[d] * rinv * cz[sl];
+                        // 1 - rho, with cz = -invn_j: the minimised quantity
+                        v[d] = fma(S[d] * rinv, cz[sl], (F)1);
                     }
                 }
                 reduce_step(tau, q + 1, v);
@@ -444,7 +511,7 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                     for (int u = 0; u < KD; ++u) {
                         rxs[u] = xr[KD + u];
                         rys[u] = yr[KD + u];
-                        rzs[u] = (KIND == ACAMP) ? -zr[KD + u] : 0.0;
+                        rzs[u] = (KIND == ACAMP) ? -zr[KD + u] : (F)0;
                     }
                 }
                 // tb is a multiple of KD and NRB divides KD: (tau + 1) % NRB == (q + 1) % NRB
@@ -463,12 +530,11 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         // holds local column tb + 1 + KD lane + d
 #pragma unroll
         for (int d = 0; d < KD; ++d) {
-            const double v = colacc[(1 + d) % KD];
+            const F v = colacc[(1 + d) % KD];
             const int64_t j = cb + tb + 1 + (int64_t)KD * lane + d;
-            if (j < N && flushable(KIND, v)) {
-                const unsigned long long kb = (unsigned long long)__double_as_longlong(v);
-                const int64_t i = j - k_lo - (int64_t)(kb & (uint64_t)(WD - 1));
-                atomicMin(&s.keys[j], pack_key(to_minimised(KIND, v), (unsigned long long)i, gmask));
+            if (j < N && P::flushable(KIND, v)) {
+                const int64_t i = j - k_lo - (int64_t)(P::index(v) & (uint32_t)(WD - 1));
+                atomicMin(&s.keys[j], pack_key((double)v, (unsigned long long)i, gmask));
             }
         }
         lds_order();
@@ -511,17 +577,17 @@ hipError_t launch_plan(const Series &s, const BandPlan &bp, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int KD>
+template <int KD, typename F>
 static hipError_t launch_kd(const Series &s, const BandPlan &bp, int32_t grid, hipStream_t st)
 {
     if (s.kind == AAMP)
-        hipLaunchKernelGGL((k_sweep_band<AAMP, P_TWO, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+        hipLaunchKernelGGL((k_sweep_band<AAMP, P_TWO, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
     else if (s.kind == ACAMP)
-        hipLaunchKernelGGL((k_sweep_band<ACAMP, P_TWO, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+        hipLaunchKernelGGL((k_sweep_band<ACAMP, P_TWO, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
     else if (s.pclass == P_ONE)
-        hipLaunchKernelGGL((k_sweep_band<PNORM, P_ONE, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+        hipLaunchKernelGGL((k_sweep_band<PNORM, P_ONE, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
     else if (s.pclass == P_THREE)
-        hipLaunchKernelGGL((k_sweep_band<PNORM, P_THREE, KD>), dim3(grid), dim3(64), 0, st, s, bp);
+        hipLaunchKernelGGL((k_sweep_band<PNORM, P_THREE, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -530,36 +596,42 @@ static hipError_t launch_kd(const Series &s, const BandPlan &bp, int32_t grid, h
 hipError_t launch_sweep_band(const Series &s, const BandPlan &bp, int32_t diags_per_lane,
                              int32_t grid, hipStream_t st)
 {
-    if (diags_per_lane == 8) return launch_kd<8>(s, bp, grid, st);
-    if (diags_per_lane == 16) return launch_kd<16>(s, bp, grid, st);
+    if (s.fp32) {
+        if (diags_per_lane == 8) return launch_kd<8, float>(s, bp, grid, st);
+        if (diags_per_lane == 16) return launch_kd<16, float>(s, bp, grid, st);
+    } else {
+        if (diags_per_lane == 8) return launch_kd<8, double>(s, bp, grid, st);
+        if (diags_per_lane == 16) return launch_kd<16, double>(s, bp, grid, st);
+    }
     return hipErrorInvalidValue;
 }
 
-template <int KD>
+template <int KD, typename F>
 static int32_t occupancy_kd(const Series &s)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     if (s.kind == AAMP)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<AAMP, P_TWO, KD>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<AAMP, P_TWO, KD, F>, 64, 0);
     else if (s.kind == ACAMP)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<ACAMP, P_TWO, KD>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<ACAMP, P_TWO, KD, F>, 64, 0);
     else if (s.pclass == P_ONE)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_ONE, KD>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_ONE, KD, F>, 64, 0);
     else if (s.pclass == P_THREE)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_THREE, KD>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_THREE, KD, F>, 64, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 int32_t band_blocks_per_cu(const Series &s, int32_t diags_per_lane)
 {
-    return diags_per_lane == 16 ? occupancy_kd<16>(s) : occupancy_kd<8>(s);
+    if (s.fp32) return diags_per_lane == 16 ? occupancy_kd<16, float>(s) : occupancy_kd<8, float>(s);
+    return diags_per_lane == 16 ? occupancy_kd<16, double>(s) : occupancy_kd<8, double>(s);
 }
 
 int32_t band_lds_bytes(int32_t kind, int32_t diags_per_lane)
 {
     const int nf = kind == ACAMP ? 3 : 2;
-    return (int32_t)(8 * (nf * 64 * diags_per_lane + NRB * 64 + 64));
+    return (int32_t)(8 * (nf * 64 * diags_per_lane + NRB * 64));
 }
 
 }  // namespace mpk

@@ -25,6 +25,10 @@ constexpr double SENT_EUCLID = -1e100;   // u = v = -1e100: each step adds ~1e20
 constexpr double SENT_P1 = -1e200;       // |a_i - a_j| ~ 1e200
 constexpr double SENT_P3 = -1e66;        // |a_i - a_j|^3 ~ 1e198
 constexpr double SENT_INIT = 1e200;      // start value of a diagonal already past N
+// float-stream sentinels (the sums of pairs touching them exceed 1e30 or are +inf)
+constexpr float SENTF_EUCLID = -1e18f;
+constexpr float SENTF_P1 = -1e30f;
+constexpr float SENTF_P3 = -1e10f;
 
 // Device views of one prepared series.
 struct Series {
@@ -55,13 +59,41 @@ struct Series {
     unsigned long long *keys;
     // Fallback-queue counter, zeroed by the preparation kernel.
     int32_t *fb_count;
+    // FP32 copies of the streams (MP_FP32_REFRESH), recentred before rounding:
+    //   AAMP:  xf = u_j, yf = v_j - 2c;  PNORM: xf = a_j - c, yf = b_j - c;
+    //   ACAMP: xf = df_j, yf = dg_j, zf = -invn_j; c = t_0.
+    // Entries j >= N hold float-range sentinels.
+    float *xf;
+    float *yf;
+    float *zf;
+    int32_t fp32;          // 1: sweep in FP32 with FP64 restarts
+    int32_t force_fb;      // test hook: 1 queue every row for the exact search seeded
+                           // with its winner, 2 queue every row with no seed
 };
+
+// Tolerance of the FP32 sweep's self-check: the winner's FP32 key value (its
+// index tag alone may move it by 2^-14 relative) against its exact value, in
+// units of the minimised sum S. The profile value is S^(1/p), so a relative
+// error e in S is e/p in the profile: the tolerance scales with p/2 (AAMP and
+// ACAMP count as p = 2). For ACAMP the key is 1 - rho, computed next to 1, so
+// its FP32 rounding floor is a few units of 2^-24 absolute.
+constexpr double FP32_SELF_CHECK = 1.5e-4;
+constexpr double FP32_SELF_CHECK_ABS_Z = 2.5e-7;
+
+// Pivot windows of the exact fallback search (triangle-inequality pruning).
+constexpr int FB_PIVOTS = 16;
 
 // Fallback list: rows whose winner must be recomputed exactly.
 struct Fallback {
     int32_t *count;        // one counter
     int32_t *rows;         // capacity entries
+    unsigned long long *keys;   // capacity entries: best (value, index) found so far
+    double *ub;            // capacity entries: upper bound on the row's distance (+inf: none)
+    int32_t *pivots;       // FB_PIVOTS window indices (-1: unused)
+    float *pd;             // FB_PIVOTS x pd_stride: distance of every window to each pivot
+    int64_t pd_stride;
     int32_t capacity;
+    int32_t pad0;
 };
 
 // Band-sweep work decomposition (computed on the device by launch_plan).

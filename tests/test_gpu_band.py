@@ -133,3 +133,46 @@ def test_band_repeatable(mp):
     P1, I1 = _call(mp, "acamp", T, m)
     P2, I2 = _call(mp, "acamp", T, m)
     assert np.array_equal(P1, P2) and np.array_equal(I1, I2)
+
+
+# ---- FP32 sweep with FP64 restarts: profile values within 1e-4 relative ----
+
+def _check32(mp, kind, T, m, p=2.0, excl=None, R=0, label=""):
+    excl = excl or W.excl_default(m)
+    _note(f"{label}: band fp32 kind={kind} p={p} n={len(T)} m={m} excl={excl} R={R}")
+    P, I = _call(mp, kind, T, m, p=p, excl=excl, R=R, precision="fp32")
+    Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl)
+    atol = 1e-6 if kind == "acamp" else 0.0
+    return check_profile(T, m, kind, p, excl, P, I, Pr, Ir, Qr, 1e-4, atol, label=label), P, I
+
+
+@pytest.mark.parametrize("kind", ["aamp", "acamp"])
+@pytest.mark.parametrize("n", [560, 2500])
+def test_band_fp32_ragged(mp, kind, n):
+    rng = np.random.default_rng(900 + n)
+    T = np.cumsum(rng.standard_normal(n))
+    _check32(mp, kind, T, 24, label=f"fp32-{kind}-{n}")
+
+
+@pytest.mark.parametrize("R", [16, 200, 1024])
+def test_band_fp32_refresh_intervals(mp, R):
+    rng = np.random.default_rng(950 + R)
+    T = np.cumsum(rng.standard_normal(3000))
+    _check32(mp, "aamp", T, 48, R=R, label=f"fp32-R{R}")
+    _check32(mp, "acamp", T, 48, R=R, label=f"fp32-R{R}z")
+
+
+@pytest.mark.parametrize("p", [1.0, 3.0])
+def test_band_fp32_pnorm(mp, p):
+    T, _ = W.sines(n=2600, m=32)
+    _check32(mp, "pnorm", T, 32, p=p, label=f"fp32-pnorm{p}")
+
+
+def test_band_fp32_runs_motifs_offset(mp):
+    T, m, planted = W.rw128k(n=5000, m=48, nruns=5, nmotifs=3, run_len=(80, 400))
+    T = T + 1e4          # a large offset: the FP32 streams are recentred
+    info, P, I = _check32(mp, "acamp", T, m, label="fp32-runs")
+    for s, L in planted.runs:
+        inside = np.arange(s, s + L - m + 1)
+        assert np.all(np.isinf(P[inside])) and np.all(I[inside] == -1)
+    info, P, I = _check32(mp, "aamp", T, m, label="fp32-offset-aamp")

@@ -107,3 +107,34 @@ def test_uniform_paper_shape_sampled(mp):
     T, m = W.uniform()
     N = len(T) - m + 1
     _sampled(mp, "acamp", T, m, W.sample_rows(N, 128, seed=6), label="uniform")
+
+
+@pytest.mark.parametrize("kind", ["acamp", "aamp"])
+def test_rw128k_fp32_sampled(mp, kind):
+    """FP32 sweep with FP64 restarts on the bench workload: values within
+    1e-4 relative of the oracle, indices equal unless the runner-up is within
+    that bound."""
+    T, m, planted = W.rw128k()
+    N = len(T) - m + 1
+    rows = list(W.sample_rows(N, 384, seed=12))
+    for a, b in planted.motifs:
+        rows += [a, b]
+    info, P, I = _sampled(mp, kind, T, m, rows, precision="fp32", label=f"rw128k-fp32-{kind}")
+    if kind == "acamp":
+        for a, b in planted.motifs:
+            assert I[a] == b and I[b] == a
+
+
+@pytest.mark.parametrize("p", [1.0, 3.0])
+def test_sines_pnorm_fp32_sampled(mp, p):
+    T, m = W.sines()
+    N = len(T) - m + 1
+    _sampled(mp, "pnorm", T, m, W.sample_rows(N, 256, seed=20 + int(p)), p=p, precision="fp32",
+             label=f"sines-fp32-p{p}")
+
+
+def test_ecg_fp32_sampled(mp):
+    T, m, anomalies = W.ecg()
+    N = len(T) - m + 1
+    rows = list(W.sample_rows(N, 48, seed=7)) + [max(0, c - m // 2) for c in anomalies]
+    _sampled(mp, "acamp", T, m, rows, precision="fp32", label="ecg-fp32")
