@@ -119,11 +119,25 @@ typedef struct mp_job {
 
 /*
  * mp_batch -- matrix profiles of many independent series in one persistent
- * launch of the sweep. jobs is a HOST array of njobs entries (read during the
- * call only). The first call with a given job table and precision captures the
- * whole pipeline into a HIP graph; later calls with an identical table,
- * precision, pointers and stream replay it. Output ranges of different jobs
- * must not overlap. Each job obeys the single-series rules above.
+ * launch of the sweep: the bands of diagonals of every series are laid end to
+ * end and split evenly over the waves of one grid, whatever the mix of
+ * lengths, window lengths and distances (the single-series kernels of
+ * Algorithms 1-3, extended over a job table).
+ *
+ * jobs is a HOST array of njobs entries (read during the call only),
+ * 0 <= njobs <= 65535. Each job obeys the single-series rules above; output
+ * ranges of different jobs must not overlap (MP_EINVAL otherwise). I values
+ * are local to their series.
+ *
+ * The first call with a given batch shape (the job table without its offsets,
+ * and the precision) runs the autotuner: a few trial runs of the whole batch
+ * with different band widths (diagonals per lane) and refresh intervals R
+ * (jobs with R = 0 only), keeping the fastest; its time is reported in
+ * mp_stats.ms_autotune. The first call with a given job table, precision and
+ * pointers captures the pipeline into a HIP graph; later identical calls
+ * replay it (while profiling is on the pipeline is launched directly, so that
+ * its phases can be timed). The graph runs on a library stream ordered after
+ * the caller's stream and before the caller's later work.
  */
 int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
              double *P_cat, int64_t *I_cat, void *stream);
@@ -148,16 +162,20 @@ void mp_release(void);
  */
 typedef struct mp_stats {
     double ms_prep;          /* window statistics, difference streams, key fill, work plan */
-    double ms_sweep;         /* the diagonal sweep kernel alone                 */
+    double ms_sweep;         /* the diagonal sweep kernel(s) alone              */
     double ms_finalize;      /* rescoring, certification and fallback           */
+    double ms_autotune;      /* host time spent by the batch autotuner (counted  
+                                whether or not profiling is on)                  */
     int64_t pairs;           /* admissible unordered pairs                      */
     int64_t fallback_rows;   /* rows recomputed exactly in FP64                 */
     int32_t calls;           /* calls accumulated                               */
     int32_t sweep_launches;  /* sweep kernel launches accumulated               */
-    int32_t refresh_rows;    /* R used by the most recent call                  */
+    int32_t refresh_rows;    /* R of the most recent call (its first band-swept job) */
     int32_t diags_per_lane;  /* diagonals per lane of the band kernel, most recent call */
     int32_t items;           /* work items (diagonal band x row segment), most recent call */
-    int32_t reserved;
+    int32_t graph_replays;   /* mp_batch calls served by replaying a captured graph,
+                                since the last mp_set_profiling() (counted whether
+                                or not profiling is on)                          */
 } mp_stats;
 
 void mp_set_profiling(int on);

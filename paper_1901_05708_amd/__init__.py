@@ -45,14 +45,14 @@ class MpJob(ctypes.Structure):
 
 class MpStats(ctypes.Structure):
     _fields_ = [("ms_prep", ctypes.c_double), ("ms_sweep", ctypes.c_double),
-                ("ms_finalize", ctypes.c_double), ("pairs", ctypes.c_int64),
-                ("fallback_rows", ctypes.c_int64), ("calls", ctypes.c_int32),
-                ("sweep_launches", ctypes.c_int32), ("refresh_rows", ctypes.c_int32),
-                ("diags_per_lane", ctypes.c_int32), ("items", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("ms_finalize", ctypes.c_double), ("ms_autotune", ctypes.c_double),
+                ("pairs", ctypes.c_int64), ("fallback_rows", ctypes.c_int64),
+                ("calls", ctypes.c_int32), ("sweep_launches", ctypes.c_int32),
+                ("refresh_rows", ctypes.c_int32), ("diags_per_lane", ctypes.c_int32),
+                ("items", ctypes.c_int32), ("graph_replays", ctypes.c_int32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -168,12 +168,18 @@ def batch_layout(jobs: Sequence[Job]):
     return table, t_off, out_off
 
 
-def batch(T_cat, jobs: Sequence[Job], precision="fp64", stream=None, out=None):
+def batch(T_cat, jobs: Sequence[Job], precision="fp64", stream=None, out=None, table=None):
     """Matrix profiles of many series in one call (mp_batch). T_cat is the
     concatenation of the series; returns (P_cat, I_cat) with each job's
-    outputs at its out_off (see batch_layout)."""
+    outputs at its out_off (see batch_layout). Passing the same `out` tensors
+    (and T_cat) again replays the library's captured graph of the batch;
+    `table` may hold a prebuilt batch_layout() table to skip rebuilding it."""
     import torch
-    table, total_n, total_out = batch_layout(jobs)
+    if table is None:
+        table, total_n, total_out = batch_layout(jobs)
+    else:
+        total_n = sum(jb.n for jb in jobs)
+        total_out = sum(jb.n - jb.m + 1 for jb in jobs)
     if T_cat.dtype != torch.float64 or T_cat.device.type != "cuda" or T_cat.shape[0] < total_n:
         raise TypeError("T_cat must be a float64 cuda tensor holding every series")
     T_cat = T_cat.contiguous()

@@ -1,13 +1,16 @@
-// api.hip -- host side of libmp: argument validation, per-device workspace,
-// the planner that picks the sweep kernel and its shape, and the C ABI of
-// include/mp.h.
+// api.hip -- host side of libmp: argument validation, the per-device
+// workspace, the planner that lays out a launch (one series, or a batch of
+// jobs end to end) and picks the sweep kernels and their shape, the batch
+// autotuner and graph cache, and the C ABI of include/mp.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -42,72 +45,80 @@ int fail_hip(hipError_t e, const char *where)
         if (e__ != hipSuccess) return fail_hip(e__, where); \
     } while (0)
 
+#define RC_TRY(expr)                             \
+    do {                                         \
+        int rc__ = (expr);                       \
+        if (rc__ != MP_OK) return rc__;          \
+    } while (0)
+
+// One lock for all library state (workspace, graph and tuning caches,
+// profiling records).
+std::recursive_mutex g_mu;
+
 // ---------------------------------------------------------------------------
-// per-device workspace (grow-only)
+// per-device workspace (grow-only): the per-window arrays of every series of
+// a launch, concatenated
 // ---------------------------------------------------------------------------
 struct Workspace {
-    int64_t cap = 0;           // stream entries (N + STREAM_PAD) the buffers hold
+    int64_t stream_cap = 0;            // stream entries (sum over jobs of N + STREAM_PAD)
+    int64_t key_cap = 0;               // windows (sum over jobs of N)
     double *x = nullptr, *y = nullptr, *z = nullptr;
     float *xf = nullptr, *yf = nullptr, *zf = nullptr;
     double *mu = nullptr, *invn = nullptr;
     uint8_t *isconst = nullptr;
     unsigned long long *keys = nullptr;
+    // exact-search queue (key_cap entries) and pivot distances
+    int32_t *fb_rows = nullptr;
+    int32_t *fb_job = nullptr;
     unsigned long long *fb_keys = nullptr;
     double *fb_ub = nullptr;
-    float *fb_pd = nullptr;            // FB_PIVOTS x cap pivot distances
-    int32_t *fb_pivots = nullptr;
-    int32_t *fb_rows = nullptr;
-    int32_t *counters = nullptr;       // [0] fallback count, [1..] spare
-    int64_t band_cap = 0;
-    int64_t *band_start = nullptr;
-    unsigned int *next_item = nullptr;
+    float *fb_pd = nullptr;            // FB_PIVOTS x key_cap
+    int32_t *counters = nullptr;
+    // tables of single-series calls (one job)
+    Job *job1 = nullptr;
+    int64_t *row_base1 = nullptr;
+    int32_t *flag1 = nullptr;
+    int32_t *pivots1 = nullptr;
+    int64_t *band1 = nullptr;
+    int64_t band1_cap = 0;
+    uint64_t generation = 1;           // bumped whenever the arrays above move
     int arch_ok = -1;                  // -1 unknown, 0 no, 1 gfx950
+    int cus = 0;
+    // library stream and fork / join events of graph launches
+    hipStream_t lib_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
-std::mutex g_mu;
 std::vector<Workspace> g_ws;
+
+void free_arrays(Workspace &w)
+{
+    void *ptrs[] = {w.x, w.y, w.z, w.xf, w.yf, w.zf, w.mu, w.invn, w.isconst, w.keys,
+                    w.fb_rows, w.fb_job, w.fb_keys, w.fb_ub, w.fb_pd, w.counters};
+    for (void *p : ptrs) hipFree(p);
+    w.x = w.y = w.z = w.mu = w.invn = w.fb_ub = nullptr;
+    w.xf = w.yf = w.zf = w.fb_pd = nullptr;
+    w.isconst = nullptr;
+    w.keys = w.fb_keys = nullptr;
+    w.fb_rows = w.fb_job = w.counters = nullptr;
+    w.stream_cap = w.key_cap = 0;
+    w.generation++;
+}
 
 void free_ws(Workspace &w)
 {
-    hipFree(w.x);
-    hipFree(w.y);
-    hipFree(w.z);
-    hipFree(w.xf);
-    hipFree(w.yf);
-    hipFree(w.zf);
-    hipFree(w.mu);
-    hipFree(w.invn);
-    hipFree(w.isconst);
-    hipFree(w.keys);
-    hipFree(w.fb_keys);
-    hipFree(w.fb_ub);
-    hipFree(w.fb_pd);
-    hipFree(w.fb_pivots);
-    hipFree(w.fb_rows);
-    hipFree(w.counters);
-    hipFree(w.band_start);
-    hipFree(w.next_item);
-    int arch = w.arch_ok;
-    w = Workspace();
-    w.arch_ok = arch;
-}
-
-int get_ws(Workspace **out, int *dev_out)
-{
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_mu);
-    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-    Workspace &w = g_ws[dev];
-    if (w.arch_ok < 0) {
-        hipDeviceProp_t prop;
-        HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        w.arch_ok = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 0;
-    }
-    if (!w.arch_ok) return fail(MP_EUNSUPPORTED, "the current HIP device is not a gfx950 GPU");
-    *out = &w;
-    *dev_out = dev;
-    return MP_OK;
+    free_arrays(w);
+    void *ptrs[] = {w.job1, w.row_base1, w.flag1, w.pivots1, w.band1};
+    for (void *p : ptrs) hipFree(p);
+    w.job1 = nullptr;
+    w.row_base1 = w.band1 = nullptr;
+    w.flag1 = w.pivots1 = nullptr;
+    w.band1_cap = 0;
+    if (w.ev_fork) hipEventDestroy(w.ev_fork);
+    if (w.ev_join) hipEventDestroy(w.ev_join);
+    if (w.lib_stream) hipStreamDestroy(w.lib_stream);
+    w.ev_fork = w.ev_join = nullptr;
+    w.lib_stream = nullptr;
 }
 
 template <class T>
@@ -124,44 +135,76 @@ int grow(T **p, size_t count, const char *what)
     return MP_OK;
 }
 
-int ensure_ws(Workspace &w, int64_t N)
+int get_ws(Workspace **out, int *dev_out)
 {
-    const int64_t need = N + STREAM_PAD;
-    if (w.cap >= need) return MP_OK;
-    int64_t cap = std::max<int64_t>(need, w.cap + w.cap / 2);
-    free_ws(w);
-    int rc;
-    if ((rc = grow(&w.x, cap, "workspace x")) || (rc = grow(&w.y, cap, "workspace y")) ||
-        (rc = grow(&w.z, cap, "workspace z")) || (rc = grow(&w.xf, cap, "workspace xf")) ||
-        (rc = grow(&w.yf, cap, "workspace yf")) || (rc = grow(&w.zf, cap, "workspace zf")) ||
-        (rc = grow(&w.mu, cap, "workspace mu")) ||
-        (rc = grow(&w.invn, cap, "workspace invn")) ||
-        (rc = grow(&w.isconst, cap, "workspace const")) ||
-        (rc = grow(&w.keys, cap, "workspace keys")) ||
-        (rc = grow(&w.fb_keys, cap, "workspace fallback keys")) ||
-        (rc = grow(&w.fb_ub, cap, "workspace fallback bounds")) ||
-        (rc = grow(&w.fb_pd, (size_t)cap * FB_PIVOTS, "workspace pivot distances")) ||
-        (rc = grow(&w.fb_pivots, 64, "workspace pivots")) ||
-        (rc = grow(&w.fb_rows, cap, "workspace fallback")) ||
-        (rc = grow(&w.counters, 64, "workspace counters")) ||
-        (rc = grow(&w.next_item, 64, "workspace counter"))) {
-        free_ws(w);
-        return rc;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    Workspace &w = g_ws[dev];
+    if (w.arch_ok < 0) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        w.arch_ok = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 0;
+        w.cus = prop.multiProcessorCount;
     }
-    w.cap = cap;
+    if (!w.arch_ok) return fail(MP_EUNSUPPORTED, "the current HIP device is not a gfx950 GPU");
+    if (!w.job1) {
+        RC_TRY(grow(&w.job1, 1, "workspace job table"));
+        RC_TRY(grow(&w.row_base1, 4, "workspace job table"));
+        RC_TRY(grow(&w.flag1, 1, "workspace job table"));
+        RC_TRY(grow(&w.pivots1, FB_PIVOTS, "workspace job table"));
+    }
+    *out = &w;
+    *dev_out = dev;
     return MP_OK;
 }
 
-int ensure_bands(Workspace &w, int64_t nbands)
+int ensure_arrays(Workspace &w, int64_t streams, int64_t keys)
 {
-    if (w.band_cap >= nbands + 1) return MP_OK;
-    int64_t cap = std::max<int64_t>(nbands + 1, 4096);
-    int rc = grow(&w.band_start, cap, "workspace bands");
-    if (rc) {
-        w.band_cap = 0;
+    if (w.stream_cap >= streams && w.key_cap >= keys) return MP_OK;
+    const int64_t scap = std::max<int64_t>(streams, w.stream_cap + w.stream_cap / 2);
+    const int64_t kcap = std::max<int64_t>(keys, w.key_cap + w.key_cap / 2);
+    free_arrays(w);
+    int rc;
+    if ((rc = grow(&w.x, scap, "workspace x")) || (rc = grow(&w.y, scap, "workspace y")) ||
+        (rc = grow(&w.z, scap, "workspace z")) || (rc = grow(&w.xf, scap, "workspace xf")) ||
+        (rc = grow(&w.yf, scap, "workspace yf")) || (rc = grow(&w.zf, scap, "workspace zf")) ||
+        (rc = grow(&w.mu, kcap, "workspace mu")) || (rc = grow(&w.invn, kcap, "workspace invn")) ||
+        (rc = grow(&w.isconst, kcap, "workspace const")) ||
+        (rc = grow(&w.keys, kcap, "workspace keys")) ||
+        (rc = grow(&w.fb_rows, kcap, "workspace fallback rows")) ||
+        (rc = grow(&w.fb_job, kcap, "workspace fallback jobs")) ||
+        (rc = grow(&w.fb_keys, kcap, "workspace fallback keys")) ||
+        (rc = grow(&w.fb_ub, kcap, "workspace fallback bounds")) ||
+        (rc = grow(&w.fb_pd, (size_t)kcap * FB_PIVOTS, "workspace pivot distances")) ||
+        (rc = grow(&w.counters, 64, "workspace counters"))) {
+        free_arrays(w);
         return rc;
     }
-    w.band_cap = cap;
+    w.stream_cap = scap;
+    w.key_cap = kcap;
+    return MP_OK;
+}
+
+int ensure_band1(Workspace &w, int64_t entries)
+{
+    if (w.band1_cap >= entries) return MP_OK;
+    const int64_t cap = std::max<int64_t>(entries, 4096);
+    int rc = grow(&w.band1, cap, "workspace bands");
+    if (rc) {
+        w.band1_cap = 0;
+        return rc;
+    }
+    w.band1_cap = cap;
+    return MP_OK;
+}
+
+int ensure_lib_stream(Workspace &w)
+{
+    if (w.lib_stream) return MP_OK;
+    HIP_TRY(hipStreamCreateWithFlags(&w.lib_stream, hipStreamNonBlocking), "hipStreamCreate");
+    HIP_TRY(hipEventCreateWithFlags(&w.ev_fork, hipEventDisableTiming), "hipEventCreate");
+    HIP_TRY(hipEventCreateWithFlags(&w.ev_join, hipEventDisableTiming), "hipEventCreate");
     return MP_OK;
 }
 
@@ -178,12 +221,10 @@ struct Prof {
     std::vector<EvSet> pending;
     mp_stats acc{};
 };
-std::mutex g_prof_mu;
 Prof g_prof;
 
 int prof_begin(hipStream_t st, EvSet *es, bool *active)
 {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
     *active = g_prof.on;
     if (!*active) return MP_OK;
     for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&es->ev[k]), "hipEventCreate");
@@ -192,18 +233,6 @@ int prof_begin(hipStream_t st, EvSet *es, bool *active)
     *es->fb_host = 0;
     HIP_TRY(hipEventRecord(es->ev[0], st), "hipEventRecord");
     return MP_OK;
-}
-
-void prof_end(const EvSet &es, const mp_stats &cfg)
-{
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof.pending.push_back(es);
-    g_prof.acc.calls += 1;
-    g_prof.acc.sweep_launches += cfg.sweep_launches;
-    g_prof.acc.pairs += cfg.pairs;
-    g_prof.acc.refresh_rows = cfg.refresh_rows;
-    g_prof.acc.diags_per_lane = cfg.diags_per_lane;
-    g_prof.acc.items = cfg.items;
 }
 
 // ---------------------------------------------------------------------------
@@ -225,19 +254,6 @@ int64_t pair_count(int64_t N, int64_t excl)
     return k * (k + 1) / 2;
 }
 
-int validate(const double *T, int64_t n, int32_t m, int32_t precision, int32_t R,
-             const double *P, const int64_t *I)
-{
-    if (!T || !P || !I) return fail(MP_EINVAL, "null pointer argument");
-    if (n < 1) return fail(MP_EINVAL, "n must be >= 1");
-    if (n >= MP_MAX_N) return fail(MP_EINVAL, "n must be < 2^31");
-    if (m < 1 || (int64_t)m > n) return fail(MP_EINVAL, "m must satisfy 1 <= m <= n");
-    if (precision != MP_FP64 && precision != MP_FP32_REFRESH)
-        return fail(MP_EINVAL, "precision must be MP_FP64 or MP_FP32_REFRESH");
-    if (R < 0) return fail(MP_EINVAL, "R must be >= 0");
-    return MP_OK;
-}
-
 int32_t pclass_of(double p)
 {
     if (p == 1.0) return P_ONE;
@@ -246,36 +262,70 @@ int32_t pclass_of(double p)
     return P_GENERIC;
 }
 
-const char *sweep_choice()
+// One validated series request.
+struct Spec {
+    const double *T;
+    int64_t n;
+    int32_t m, kind, pclass, excl, R;
+    double p;
+    double *P;
+    int64_t *I;
+};
+
+int make_spec(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
+              int32_t R, double *P, int64_t *I, Spec *out)
 {
-    const char *e = std::getenv("MP_SWEEP");
-    return e ? e : "auto";
+    if (!T || !P || !I) return fail(MP_EINVAL, "null pointer argument");
+    if (n < 1) return fail(MP_EINVAL, "n must be >= 1");
+    if (n >= MP_MAX_N) return fail(MP_EINVAL, "n must be < 2^31");
+    if (m < 1 || (int64_t)m > n) return fail(MP_EINVAL, "m must satisfy 1 <= m <= n");
+    if (R < 0) return fail(MP_EINVAL, "R must be >= 0");
+    if (kind < AAMP || kind > ACAMP) return fail(MP_EINVAL, "kind must be MP_KIND_*");
+    if (kind == PNORM && !(std::isfinite(p) && p >= 1.0))
+        return fail(MP_EINVAL, "p must be finite and >= 1");
+    Spec s;
+    s.T = T;
+    s.n = n;
+    s.m = m;
+    s.kind = (kind == PNORM && p == 2.0) ? AAMP : kind;   // Sec. 3.3: p = 2 is Euclid
+    s.p = s.kind == PNORM ? p : 2.0;
+    s.pclass = s.kind == PNORM ? pclass_of(p) : P_TWO;
+    s.excl = excl > 0 ? excl : (m + 3) / 4;
+    s.R = R;
+    s.P = P;
+    s.I = I;
+    *out = s;
+    return MP_OK;
 }
 
-struct Plan {
-    bool band = false;
-    int32_t R = 0;
-    int32_t diags_per_lane = 0;
-    int32_t grid = 0;
-    int64_t nbands = 0;
-    int64_t items = 0;
-};
-
-struct DevInfo {
-    int cus = 0;
-};
-std::vector<DevInfo> g_dev;
-
-int device_cus(int dev)
+int check_precision(int32_t precision)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
-    if (g_dev[dev].cus == 0) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-        g_dev[dev].cus = prop.multiProcessorCount;
+    if (precision != MP_FP64 && precision != MP_FP32_REFRESH)
+        return fail(MP_EINVAL, "precision must be MP_FP64 or MP_FP32_REFRESH");
+    return MP_OK;
+}
+
+// Shape knobs of a launch: diagonals per lane (band width / 64), the refresh
+// interval of jobs that leave R to the library (0: per-distance default) and
+// the persistent grid as a multiple of the resident waves.
+struct Tuning {
+    int32_t kd = 8;
+    int32_t R = 0;
+    int32_t grid_mult = 1;
+};
+
+// Default refresh intervals. FP64 drift is far below its 1e-9 bound at any
+// practical R, so R only trades the restart cost (2m per diagonal) against
+// item count. In FP32 every step can add 2^-24 relative error; the values
+// below minimise sweep plus exact-search time on the series shapes measured.
+int32_t default_R(uint32_t sel, bool fp32)
+{
+    if (!fp32) return 4096;
+    switch (sel) {
+    case SEL_ACAMP: return 512;
+    case SEL_P1: return 1024;
+    default: return 256;
     }
-    return g_dev[dev].cus;
 }
 
 // Rows summed over all bands (band b: N - excl - b W rows) and the band count.
@@ -284,152 +334,585 @@ int64_t band_rows_total(int64_t N, int64_t excl, int64_t W, int64_t *nbands)
     const int64_t nd = N - excl;
     const int64_t nb = (nd + W - 1) / W;
     *nbands = nb;
-    // sum_{b < nb} (nd - b W)
     return nb * nd - W * (nb * (nb - 1) / 2);
 }
 
-// Kernel and shape. The band kernel needs at least half a band of diagonals.
-// Its persistent grid gives every wave an equal share of the band-major row
-// space; R bounds the rows between exact FP64 restarts (each restart costs 2m
-// operations per diagonal, and longer runs let round-off drift further).
-int make_plan(const Series &s, int32_t R_user, int dev, Plan *pl)
-{
-    const int64_t ndiag = s.N - s.excl;
-    Plan p;
-    std::string choice = sweep_choice();
+// Windows shorter than this are swept in FP64 even under MP_FP32_REFRESH: with
+// few terms per window the running sum can shrink by orders of magnitude
+// within a few steps, and the error it carried from its larger past is then
+// amplified far beyond what the winner's self-check can see.
+constexpr int32_t FP32_MIN_M = 32;
+
+// A band sweep of a launch: a contiguous range of the job table, all in one
+// precision, with its own band-row space.
+struct Group {
+    int32_t first = 0, count = 0;
+    int64_t rows = 0;
+    int64_t rb_off = 0;        // its row_base entries (count + 1) in the table
+    uint32_t sels = 0;
+    int32_t grid = 0;
+};
+
+// A launch laid out: the job table (pointers bound to a workspace by bind())
+// ordered as [FP64 band jobs][FP32 band jobs][other jobs], the two band
+// sweeps' row_base prefixes, and the sizes of every per-launch array.
+struct Layout {
+    std::vector<Job> jobs;
+    std::vector<int64_t> row_base;       // group 0 (count + 1), then group 1 (count + 1)
+    std::vector<int64_t> stream_off;     // per job (table order)
+    Group g[2];                          // 0: FP64 band sweep, 1: FP32 band sweep
+    int64_t band_entries = 0;
+    int64_t stream_total = 0, key_total = 0;
+    int64_t max_N = 0, max_stream = 0, simple_diag = 0, simple_segs = 0;
+    uint32_t sels = 0;
     int32_t kd = 8;
-    if (const char *e = std::getenv("MP_KD")) kd = (std::atoi(e) == 16) ? 16 : 8;
+    int64_t pairs = 0, items = 0;
+    int32_t R_report = 0;
+};
+
+int env_int(const char *name, int dflt)
+{
+    const char *e = std::getenv(name);
+    return e ? std::atoi(e) : dflt;
+}
+
+// Lay out a launch. A job goes to the band kernel when its distance has one
+// and it has at least half a band of diagonals; otherwise to the simple
+// kernel (FP64 only: a single-precision request on such a job is served
+// exactly in FP64). Test hooks: MP_SWEEP=band|simple forces a kernel,
+// MP_KD=16 requests 16 diagonals per lane (FP32 only), MP_FORCE_FALLBACK=1|2
+// sends every row through the exact search.
+int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning &tu,
+                const Workspace &w, Layout *out)
+{
+    Layout L;
+    const bool want32 = precision == MP_FP32_REFRESH;
+    const char *sw = std::getenv("MP_SWEEP");
+    const std::string choice = sw ? sw : "auto";
+    int32_t kd = tu.kd;
+    if (env_int("MP_KD", 0) == 16) kd = 16;
+    if (!want32) kd = 8;   // 16 FP64 diagonals per lane exceed the register file
     const int64_t W = 64 * kd;
-    p.band = band_supported(s) && ndiag >= W / 2 && choice != "simple";
-    if (choice == "band" && band_supported(s) && ndiag > 0) p.band = true;
-    if (ndiag <= 0) p.band = false;
-    if (p.band) {
-        p.diags_per_lane = kd;
-        const int64_t slots = (int64_t)device_cus(dev) * band_blocks_per_cu(s, kd);
-        const int64_t rows = band_rows_total(s.N, s.excl, W, &p.nbands);
-        // default refresh interval: 4096 rows in FP64; 1024 in FP32, where
-        // drift grows 2^29 times faster per step
-        int64_t R = R_user > 0 ? R_user : (s.fp32 ? 1024 : 4096);
-        p.R = (int32_t)std::min<int64_t>(R, INT32_MAX / 2);
-        // at least 64 rows per wave
-        p.grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(slots, rows / 64));
-        const int64_t share = (rows + p.grid - 1) / p.grid;
-        p.items = (int64_t)p.grid * ((share + p.R - 1) / p.R) + p.nbands;   // upper bound
-    } else {
-        // the simple kernel is FP64 only; a single-precision request on a
-        // series too small for the band kernel is served exactly in FP64
-        int32_t R = R_user > 0 ? R_user : 1024;
-        // the simple kernel's grid has one row of blocks per segment
-        int64_t minR = (ndiag + 65534) / 65535;
-        if (R < minR) R = (int32_t)minR;
-        p.R = R;
+    int force_fb = env_int("MP_FORCE_FALLBACK", 0);
+    if (force_fb != 1 && force_fb != 2) force_fb = 0;
+
+    std::vector<Job> cls[3];          // FP64 band, FP32 band, other
+    std::vector<int64_t> rows_of[3];
+    for (const Spec &sp : specs) {
+        Job j;
+        std::memset(&j, 0, sizeof(j));
+        Series &s = j.s;
+        s.T = sp.T;
+        s.n = sp.n;
+        s.N = sp.n - sp.m + 1;
+        s.m = sp.m;
+        s.kind = sp.kind;
+        s.pclass = sp.pclass;
+        s.excl = sp.excl;
+        s.p = sp.p;
+        s.gb = index_bits(s.N);
+        s.force_fb = force_fb;
+        j.P = sp.P;
+        j.I = sp.I;
+        const uint32_t sel = sel_of(s.kind, s.pclass);
+        const int64_t ndiag = s.N - s.excl;
+        bool band = (sel & SEL_BAND) && ndiag >= W / 2 && choice != "simple";
+        if (choice == "band" && (sel & SEL_BAND) && ndiag > 0) band = true;
+        if (ndiag <= 0) band = false;
+        s.fp32 = (want32 && band && s.m >= FP32_MIN_M) ? 1 : 0;
+        int64_t rows = 0, nb = 0;
+        if (band) {
+            rows = band_rows_total(s.N, s.excl, W, &nb);
+            int64_t R = sp.R > 0 ? sp.R : (tu.R > 0 && s.fp32 == want32 ? tu.R : default_R(sel, s.fp32));
+            j.seg_rows = (int32_t)std::min<int64_t>(R, INT32_MAX / 2);
+            if (L.R_report == 0) L.R_report = j.seg_rows;
+        } else if (ndiag > 0) {
+            // the simple kernel's grid has one row of blocks per segment
+            int64_t R = sp.R > 0 ? sp.R : 1024;
+            R = std::max<int64_t>(R, (ndiag + 65534) / 65535);
+            j.seg_rows = (int32_t)R;
+            L.simple_diag = std::max(L.simple_diag, ndiag);
+            L.simple_segs = std::max(L.simple_segs, (ndiag + R - 1) / R);
+        }
+        j.nbands = (int32_t)nb;
+        L.sels |= sel;
+        L.pairs += pair_count(s.N, s.excl);
+        L.items += nb + (band ? rows / j.seg_rows : 0);
+        const int c = band ? (s.fp32 ? 1 : 0) : 2;
+        cls[c].push_back(j);
+        rows_of[c].push_back(rows);
     }
-    *pl = p;
+    for (int c = 0; c < 3; ++c) {
+        if (c < 2) {
+            Group &g = L.g[c];
+            g.first = (int32_t)L.jobs.size();
+            g.count = (int32_t)cls[c].size();
+            g.rb_off = (int64_t)L.row_base.size();
+        }
+        int64_t run = 0;
+        for (size_t k = 0; k < cls[c].size(); ++k) {
+            Job j = cls[c][k];
+            const Series &s = j.s;
+            j.row_start = run;
+            if (c < 2) L.row_base.push_back(run);
+            run += rows_of[c][k];
+            j.band_base = L.band_entries;
+            L.band_entries += j.nbands + 1;
+            j.key_base = L.key_total;
+            L.stream_off.push_back(L.stream_total);
+            L.key_total += s.N;
+            L.stream_total += s.N + STREAM_PAD;
+            L.max_N = std::max(L.max_N, s.N);
+            L.max_stream = std::max(L.max_stream, s.N + STREAM_PAD);
+            if (c < 2) L.g[c].sels |= sel_of(s.kind, s.pclass);
+            L.jobs.push_back(j);
+        }
+        if (c < 2) {
+            L.row_base.push_back(run);
+            L.g[c].rows = run;
+        }
+    }
+    L.kd = kd;
+    for (int c = 0; c < 2; ++c) {
+        Group &g = L.g[c];
+        if (!g.count || !g.rows) continue;
+        const int32_t gkd = c == 1 ? kd : 8;
+        const int64_t slots = (int64_t)w.cus * band_blocks_per_cu(g.sels, gkd, c == 1);
+        // at least 64 rows per wave
+        g.grid = (int32_t)std::max<int64_t>(
+            1, std::min<int64_t>(slots * std::max(1, tu.grid_mult), g.rows / 64));
+        L.items += g.grid;
+    }
+    *out = std::move(L);
     return MP_OK;
 }
 
+// Point every job at its slices of the workspace.
+void bind(Layout &L, const Workspace &w)
+{
+    for (size_t b = 0; b < L.jobs.size(); ++b) {
+        Series &s = L.jobs[b].s;
+        const int64_t so = L.stream_off[b], ko = L.jobs[b].key_base;
+        s.x = w.x + so;
+        s.y = w.y + so;
+        s.z = w.z + so;
+        s.xf = w.xf + so;
+        s.yf = w.yf + so;
+        s.zf = w.zf + so;
+        s.mu = w.mu + ko;
+        s.invn = w.invn + ko;
+        s.isconst = w.isconst + ko;
+        s.keys = w.keys + ko;
+    }
+}
+
+// Device tables of a launch.
+struct Tables {
+    Job *jobs = nullptr;
+    int64_t *row_base = nullptr;
+    int64_t *band = nullptr;
+    int32_t *flags = nullptr;
+    int32_t *pivots = nullptr;
+};
+
+Batch make_batch(const Layout &L, const Workspace &w, const Tables &t)
+{
+    Batch b;
+    std::memset(&b, 0, sizeof(b));
+    b.jobs = t.jobs;
+    b.row_base = t.row_base;
+    b.band_start = t.band;
+    b.njobs = (int32_t)L.jobs.size();
+    b.band_width = 64 * 8;
+    b.max_N = L.max_N;
+    b.max_stream = L.max_stream;
+    b.simple_diag = L.simple_diag;
+    b.simple_segs = L.simple_segs;
+    Fallback &fb = b.fb;
+    fb.count = w.counters;
+    fb.rows = w.fb_rows;
+    fb.job = w.fb_job;
+    fb.keys = w.fb_keys;
+    fb.ub = w.fb_ub;
+    fb.job_flag = t.flags;
+    fb.pivots = t.pivots;
+    fb.pd = w.fb_pd;
+    fb.pd_stride = w.key_cap;
+    fb.capacity = (int32_t)std::min<int64_t>(L.key_total, INT32_MAX);
+    return b;
+}
+
+// Diagonals per lane of a band sweep: 16 is an FP32 option only.
+int32_t group_kd(const Layout &L, int c) { return c == 1 ? L.kd : 8; }
+
+// The view of a launch that one band sweep works on.
+Batch group_view(const Batch &b, const Layout &L, int c)
+{
+    Batch v = b;
+    const Group &g = L.g[c];
+    v.jobs = b.jobs + g.first;
+    v.njobs = g.count;
+    v.row_base = b.row_base + g.rb_off;
+    v.band_width = 64 * group_kd(L, c);
+    return v;
+}
+
+// The pipeline of a launch, enqueued on st: band tables, window statistics and
+// difference streams, sweeps, rescoring and the exact search. With es,
+// records its events after the preparation, the sweeps and the whole pipeline
+// (ev[0] is recorded by the caller).
+int enqueue(const Batch &b, const Layout &L, hipStream_t st, EvSet *es)
+{
+    for (int c = 0; c < 2; ++c)
+        if (L.g[c].count) HIP_TRY(launch_plan(group_view(b, L, c), st), "plan launch");
+    HIP_TRY(launch_prep(b, L.sels, st), "prep launch");
+    if (es) HIP_TRY(hipEventRecord(es->ev[1], st), "hipEventRecord");
+    for (int c = 0; c < 2; ++c)
+        if (L.g[c].grid)
+            HIP_TRY(launch_sweep_band(group_view(b, L, c), L.g[c].sels, group_kd(L, c), c == 1,
+                                      L.g[c].grid, st),
+                    "sweep launch");
+    if (L.simple_diag > 0) HIP_TRY(launch_sweep_simple(b, st), "sweep launch");
+    if (es) HIP_TRY(hipEventRecord(es->ev[2], st), "hipEventRecord");
+    HIP_TRY(launch_finalize(b, st), "finalize launch");
+    HIP_TRY(launch_fallback(b, st), "fallback launch");
+    return MP_OK;
+}
+
+int finish_profile(EvSet &es, const Batch &b, const Layout &L, hipStream_t st)
+{
+    HIP_TRY(hipMemcpyAsync(es.fb_host, b.fb.count, sizeof(int32_t), hipMemcpyDeviceToHost, st),
+            "hipMemcpyAsync");
+    HIP_TRY(hipEventRecord(es.ev[3], st), "hipEventRecord");
+    g_prof.pending.push_back(es);
+    mp_stats &a = g_prof.acc;
+    a.calls += 1;
+    a.sweep_launches += (L.g[0].grid ? 1 : 0) + (L.g[1].grid ? 1 : 0) + (L.simple_diag > 0 ? 1 : 0);
+    a.pairs += L.pairs;
+    a.refresh_rows = L.R_report;
+    a.diags_per_lane = L.g[1].grid ? L.kd : (L.g[0].grid ? 8 : 0);
+    a.items = (int32_t)std::min<int64_t>(L.items, INT32_MAX);
+    return MP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single series: a batch of one job, tables written on the stream
+// ---------------------------------------------------------------------------
 int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
                int32_t precision, int32_t R, double *P, int64_t *I, void *stream)
 {
-    int rc = validate(T, n, m, precision, R, P, I);
-    if (rc) return rc;
-    if (kind == PNORM && !(std::isfinite(p) && p >= 1.0))
-        return fail(MP_EINVAL, "p must be finite and >= 1");
-    if (excl <= 0) excl = (m + 3) / 4;
-    if (kind == PNORM && p == 2.0) kind = AAMP;  // Sec. 3.3: p = 2 is Euclid
-
+    Spec sp;
+    RC_TRY(make_spec(T, n, m, kind, p, excl, R, P, I, &sp));
+    RC_TRY(check_precision(precision));
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     Workspace *w = nullptr;
     int dev = 0;
-    if ((rc = get_ws(&w, &dev))) return rc;
+    RC_TRY(get_ws(&w, &dev));
     hipStream_t st = (hipStream_t)stream;
-    const int64_t N = n - m + 1;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        if ((rc = ensure_ws(*w, N))) return rc;
-    }
 
-    Series s;
-    std::memset(&s, 0, sizeof(s));
-    s.T = T;
-    s.n = n;
-    s.N = N;
-    s.m = m;
-    s.kind = kind;
-    s.pclass = kind == PNORM ? pclass_of(p) : P_TWO;
-    s.excl = excl;
-    s.p = p;
-    s.gb = index_bits(N);
-    s.x = w->x;
-    s.y = w->y;
-    s.z = w->z;
-    s.mu = w->mu;
-    s.invn = w->invn;
-    s.isconst = w->isconst;
-    s.keys = w->keys;
-    s.fb_count = w->counters;
-    s.xf = w->xf;
-    s.yf = w->yf;
-    s.zf = w->zf;
-    s.fp32 = (precision == MP_FP32_REFRESH) ? 1 : 0;
-    // MP_FORCE_FALLBACK (tests): send every row through the exact search.
-    if (const char *e = std::getenv("MP_FORCE_FALLBACK")) {
-        const int v = std::atoi(e);
-        s.force_fb = (v == 1 || v == 2) ? v : 0;
-    }
-
-    Fallback fb;
-    fb.count = w->counters;
-    fb.rows = w->fb_rows;
-    fb.keys = w->fb_keys;
-    fb.ub = w->fb_ub;
-    fb.pivots = w->fb_pivots;
-    fb.pd = w->fb_pd;
-    fb.pd_stride = w->cap;
-    fb.capacity = (int32_t)std::min<int64_t>(N, INT32_MAX);
-
-    Plan pl;
-    if ((rc = make_plan(s, R, dev, &pl))) return rc;
-    if (!pl.band) s.fp32 = 0;
-    BandPlan bp;
-    std::memset(&bp, 0, sizeof(bp));
-    if (pl.band) {
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            if ((rc = ensure_bands(*w, pl.nbands))) return rc;
-        }
-        bp.band_width = 64 * pl.diags_per_lane;
-        bp.seg_rows = pl.R;
-        bp.nbands = (int32_t)pl.nbands;
-        bp.band_start = w->band_start;
-    }
+    Layout L;
+    RC_TRY(make_layout({sp}, precision, Tuning(), *w, &L));
+    RC_TRY(ensure_arrays(*w, L.stream_total, L.key_total));
+    RC_TRY(ensure_band1(*w, L.band_entries));
+    bind(L, *w);
+    Tables t;
+    t.jobs = w->job1;
+    t.row_base = w->row_base1;
+    t.band = w->band1;
+    t.flags = w->flag1;
+    t.pivots = w->pivots1;
+    const Batch b = make_batch(L, *w, t);
 
     EvSet es;
     bool prof = false;
-    if ((rc = prof_begin(st, &es, &prof))) return rc;
+    RC_TRY(prof_begin(st, &es, &prof));
+    RowBase4 rb;
+    std::memset(&rb, 0, sizeof(rb));
+    rb.count = (int32_t)L.row_base.size();
+    for (int32_t k = 0; k < rb.count && k < 4; ++k) rb.v[k] = L.row_base[k];
+    HIP_TRY(launch_store_job(L.jobs[0], rb, w->job1, w->row_base1, st), "job table");
+    RC_TRY(enqueue(b, L, st, prof ? &es : nullptr));
+    if (prof) RC_TRY(finish_profile(es, b, L, st));
+    g_last_code = MP_OK;
+    return MP_OK;
+}
 
-    HIP_TRY(launch_prep(s, st), "prep launch");
-    if (pl.band) HIP_TRY(launch_plan(s, bp, st), "plan launch");
-    if (prof) HIP_TRY(hipEventRecord(es.ev[1], st), "hipEventRecord");
-    if (pl.band) {
-        HIP_TRY(launch_sweep_band(s, bp, pl.diags_per_lane, pl.grid, st), "sweep launch");
+// ---------------------------------------------------------------------------
+// batches: autotuner, uploaded tables and captured graphs
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+    int dev;
+    int32_t precision;
+    std::vector<int64_t> shape;   // per job: n, m, kind, excl, R, p bits
+    Tuning best;
+};
+std::vector<TuneEntry> g_tune;
+
+struct GraphEntry {
+    int dev = 0;
+    int32_t precision = 0;
+    std::vector<mp_job> table;
+    const double *T = nullptr;
+    const double *P = nullptr;
+    const int64_t *I = nullptr;
+    uint64_t generation = 0;
+    Layout L;
+    Tables t;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+std::list<GraphEntry> g_graphs;      // most recently used first
+constexpr size_t GRAPH_CACHE = 16;
+
+void free_tables(Tables &t)
+{
+    hipFree(t.jobs);
+    hipFree(t.row_base);
+    hipFree(t.band);
+    hipFree(t.flags);
+    hipFree(t.pivots);
+    t = Tables();
+}
+
+void free_entry(GraphEntry &e)
+{
+    if (e.exec) hipGraphExecDestroy(e.exec);
+    if (e.graph) hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+    free_tables(e.t);
+}
+
+bool same_table(const std::vector<mp_job> &a, const mp_job *b, int32_t n)
+{
+    return (int32_t)a.size() == n && (n == 0 || std::memcmp(a.data(), b, n * sizeof(mp_job)) == 0);
+}
+
+std::vector<int64_t> shape_of(const mp_job *jobs, int32_t njobs)
+{
+    std::vector<int64_t> v;
+    v.reserve((size_t)njobs * 6);
+    for (int32_t b = 0; b < njobs; ++b) {
+        int64_t pb;
+        std::memcpy(&pb, &jobs[b].p, sizeof(pb));
+        v.insert(v.end(), {jobs[b].n, jobs[b].m, jobs[b].kind, jobs[b].excl, jobs[b].R, pb});
+    }
+    return v;
+}
+
+int upload_tables(const Layout &L, Tables *t)
+{
+    const size_t nj = L.jobs.size();
+    RC_TRY(grow(&t->jobs, nj, "batch job table"));
+    RC_TRY(grow(&t->row_base, L.row_base.size(), "batch job table"));
+    RC_TRY(grow(&t->band, (size_t)L.band_entries, "batch band table"));
+    RC_TRY(grow(&t->flags, nj, "batch job table"));
+    RC_TRY(grow(&t->pivots, nj * FB_PIVOTS, "batch job table"));
+    HIP_TRY(hipMemcpy(t->jobs, L.jobs.data(), nj * sizeof(Job), hipMemcpyHostToDevice),
+            "hipMemcpy job table");
+    HIP_TRY(hipMemcpy(t->row_base, L.row_base.data(), L.row_base.size() * sizeof(int64_t),
+                      hipMemcpyHostToDevice),
+            "hipMemcpy job table");
+    return MP_OK;
+}
+
+// Candidate shapes of the autotuner: band width (diagonals per lane; 16 only
+// fits the register file in FP32) times refresh interval.
+std::vector<Tuning> tune_candidates(int32_t precision)
+{
+    std::vector<Tuning> c;
+    if (precision == MP_FP32_REFRESH) {
+        for (int kd : {8, 16})
+            for (int R : {256, 512, 1024, 2048}) c.push_back(Tuning{kd, R, 1});
     } else {
-        HIP_TRY(launch_sweep_simple(s, pl.R, st), "sweep launch");
+        for (int R : {1024, 4096, 16384}) c.push_back(Tuning{8, R, 1});
     }
-    if (prof) HIP_TRY(hipEventRecord(es.ev[2], st), "hipEventRecord");
-    HIP_TRY(launch_finalize(s, fb, P, I, st), "finalize launch");
-    HIP_TRY(launch_fallback(s, fb, P, I, st), "fallback launch");
-    if (prof) {
-        HIP_TRY(hipMemcpyAsync(es.fb_host, fb.count, sizeof(int32_t), hipMemcpyDeviceToHost, st),
-                "hipMemcpyAsync");
-        HIP_TRY(hipEventRecord(es.ev[3], st), "hipEventRecord");
-        mp_stats cfg{};
-        cfg.pairs = pair_count(N, excl);
-        cfg.sweep_launches = 1;
-        cfg.refresh_rows = pl.R;
-        cfg.diags_per_lane = pl.band ? pl.diags_per_lane : 0;
-        cfg.items = (int32_t)std::min<int64_t>(pl.items, INT32_MAX);
-        prof_end(es, cfg);
+    return c;
+}
+
+int record(hipEvent_t e, hipStream_t s)
+{
+    HIP_TRY(hipEventRecord(e, s), "hipEventRecord");
+    return MP_OK;
+}
+
+// One timed run of a candidate (after an untimed one) on stream ls.
+int time_candidate(const std::vector<Spec> &specs, int32_t precision, const Tuning &tu,
+                   Workspace &w, hipStream_t ls, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    Layout L;
+    RC_TRY(make_layout(specs, precision, tu, w, &L));
+    RC_TRY(ensure_arrays(w, L.stream_total, L.key_total));
+    bind(L, w);
+    Tables t;
+    int rc = upload_tables(L, &t);
+    if (!rc) {
+        const Batch b = make_batch(L, w, t);
+        if (!(rc = enqueue(b, L, ls, nullptr)) && !(rc = record(e0, ls)) &&
+            !(rc = enqueue(b, L, ls, nullptr)) && !(rc = record(e1, ls))) {
+            hipError_t e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+            if (e != hipSuccess) rc = fail_hip(e, "autotune timing");
+        }
+        hipError_t es = hipStreamSynchronize(ls);
+        if (!rc && es != hipSuccess) rc = fail_hip(es, "autotune");
     }
+    free_tables(t);
+    return rc;
+}
+
+// Time every candidate on the batch itself, on the library stream after the
+// caller's pending work, and keep the fastest. The runs write the caller's
+// outputs, which the real run overwrites.
+int autotune(const std::vector<Spec> &specs, int32_t precision, Workspace &w, hipStream_t caller,
+             Tuning *best)
+{
+    RC_TRY(ensure_lib_stream(w));
+    hipStream_t ls = w.lib_stream;
+    HIP_TRY(hipEventRecord(w.ev_fork, caller), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(ls, w.ev_fork, 0), "hipStreamWaitEvent");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(MP_EHIP, "hipEventCreate");
+    }
+    float best_ms = -1.0f;
+    int rc = MP_OK;
+    for (const Tuning &tu : tune_candidates(precision)) {
+        float ms = 0.0f;
+        if ((rc = time_candidate(specs, precision, tu, w, ls, e0, e1, &ms))) break;
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            *best = tu;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
+int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
+              double *P_cat, int64_t *I_cat, void *stream)
+{
+    if (!T_cat || !P_cat || !I_cat || (!jobs && njobs > 0))
+        return fail(MP_EINVAL, "null pointer argument");
+    if (njobs < 0 || njobs > 65535) return fail(MP_EINVAL, "njobs must be in [0, 65535]");
+    RC_TRY(check_precision(precision));
+    std::vector<Spec> specs((size_t)njobs);
+    std::vector<std::pair<int64_t, int64_t>> outs((size_t)njobs);
+    for (int32_t b = 0; b < njobs; ++b) {
+        const mp_job &jb = jobs[b];
+        if (jb.t_off < 0 || jb.out_off < 0) return fail(MP_EINVAL, "negative job offset");
+        RC_TRY(make_spec(T_cat + jb.t_off, jb.n, jb.m, jb.kind, jb.p, jb.excl, jb.R,
+                         P_cat + jb.out_off, I_cat + jb.out_off, &specs[b]));
+        outs[b] = {jb.out_off, jb.out_off + (jb.n - jb.m + 1)};
+    }
+    std::sort(outs.begin(), outs.end());
+    for (size_t b = 1; b < outs.size(); ++b)
+        if (outs[b].first < outs[b - 1].second)
+            return fail(MP_EINVAL, "output ranges of two jobs overlap");
+    if (njobs == 0) {
+        g_last_code = MP_OK;
+        return MP_OK;
+    }
+
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    Workspace *w = nullptr;
+    int dev = 0;
+    RC_TRY(get_ws(&w, &dev));
+    hipStream_t st = (hipStream_t)stream;
+    RC_TRY(ensure_lib_stream(*w));
+    const bool use_graph = !g_prof.on && env_int("MP_GRAPH", 1) != 0;
+
+    // cached entry for this exact call?
+    auto it = g_graphs.begin();
+    for (; it != g_graphs.end(); ++it)
+        if (it->dev == dev && it->precision == precision && it->T == T_cat && it->P == P_cat &&
+            it->I == I_cat && same_table(it->table, jobs, njobs))
+            break;
+    if (it != g_graphs.end() && it->generation != w->generation) {
+        free_entry(*it);
+        g_graphs.erase(it);
+        it = g_graphs.end();
+    }
+    if (it == g_graphs.end()) {
+        // tuning of this batch shape
+        Tuning tu;
+        const std::vector<int64_t> shape = shape_of(jobs, njobs);
+        bool tuned = false;
+        for (const TuneEntry &te : g_tune)
+            if (te.dev == dev && te.precision == precision && te.shape == shape) {
+                tu = te.best;
+                tuned = true;
+                break;
+            }
+        if (!tuned && env_int("MP_AUTOTUNE", 1) != 0) {
+            const auto t0 = std::chrono::steady_clock::now();
+            RC_TRY(autotune(specs, precision, *w, st, &tu));
+            const auto t1 = std::chrono::steady_clock::now();
+            g_prof.acc.ms_autotune += std::chrono::duration<double, std::milli>(t1 - t0).count();
+            g_tune.push_back(TuneEntry{dev, precision, shape, tu});
+        }
+        GraphEntry e;
+        e.dev = dev;
+        e.precision = precision;
+        e.table.assign(jobs, jobs + njobs);
+        e.T = T_cat;
+        e.P = P_cat;
+        e.I = I_cat;
+        RC_TRY(make_layout(specs, precision, tu, *w, &e.L));
+        RC_TRY(ensure_arrays(*w, e.L.stream_total, e.L.key_total));
+        bind(e.L, *w);
+        int rc = upload_tables(e.L, &e.t);
+        if (rc) {
+            free_entry(e);
+            return rc;
+        }
+        e.generation = w->generation;
+        g_graphs.push_front(std::move(e));
+        it = g_graphs.begin();
+        while (g_graphs.size() > GRAPH_CACHE) {
+            free_entry(g_graphs.back());
+            g_graphs.pop_back();
+        }
+    } else if (it != g_graphs.begin()) {
+        g_graphs.splice(g_graphs.begin(), g_graphs, it);
+        it = g_graphs.begin();
+    }
+    GraphEntry &e = *it;
+    const Batch b = make_batch(e.L, *w, e.t);
+
+    if (!use_graph) {
+        EvSet es;
+        bool on = false;
+        RC_TRY(prof_begin(st, &es, &on));
+        RC_TRY(enqueue(b, e.L, st, on ? &es : nullptr));
+        if (on) RC_TRY(finish_profile(es, b, e.L, st));
+        g_last_code = MP_OK;
+        return MP_OK;
+    }
+    hipStream_t ls = w->lib_stream;
+    if (!e.exec) {
+        HIP_TRY(hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        int rc = enqueue(b, e.L, ls, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(ls, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (ec != hipSuccess) return fail_hip(ec, "hipStreamEndCapture");
+        e.graph = g;
+        HIP_TRY(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    } else {
+        g_prof.acc.graph_replays += 1;
+    }
+    HIP_TRY(hipEventRecord(w->ev_fork, st), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(ls, w->ev_fork, 0), "hipStreamWaitEvent");
+    HIP_TRY(hipGraphLaunch(e.exec, ls), "hipGraphLaunch");
+    HIP_TRY(hipEventRecord(w->ev_join, ls), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(st, w->ev_join, 0), "hipStreamWaitEvent");
     g_last_code = MP_OK;
     return MP_OK;
 }
@@ -459,21 +942,7 @@ int mp_acamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precis
 int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
              double *P_cat, int64_t *I_cat, void *stream)
 {
-    if (!T_cat || !jobs || !P_cat || !I_cat) return fail(MP_EINVAL, "null pointer argument");
-    if (njobs < 0) return fail(MP_EINVAL, "njobs must be >= 0");
-    for (int32_t b = 0; b < njobs; ++b) {
-        const mp_job &jb = jobs[b];
-        if (jb.t_off < 0 || jb.out_off < 0) return fail(MP_EINVAL, "negative job offset");
-        if (jb.kind < MP_KIND_AAMP || jb.kind > MP_KIND_ACAMP)
-            return fail(MP_EINVAL, "job kind must be MP_KIND_*");
-    }
-    for (int32_t b = 0; b < njobs; ++b) {
-        const mp_job &jb = jobs[b];
-        int rc = run_series(T_cat + jb.t_off, jb.n, jb.m, jb.kind, jb.p, jb.excl, precision, jb.R,
-                            P_cat + jb.out_off, I_cat + jb.out_off, stream);
-        if (rc) return rc;
-    }
-    return MP_OK;
+    return run_batch(T_cat, jobs, njobs, precision, P_cat, I_cat, stream);
 }
 
 const char *mp_strerror(int code)
@@ -495,13 +964,20 @@ const char *mp_strerror(int code)
 
 void mp_release(void)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (size_t d = 0; d < g_ws.size(); ++d) {
-        if (g_ws[d].cap == 0 && g_ws[d].band_cap == 0) continue;
         (void)hipSetDevice((int)d);
         (void)hipDeviceSynchronize();
+        for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+            if (it->dev == (int)d) {
+                free_entry(*it);
+                it = g_graphs.erase(it);
+            } else {
+                ++it;
+            }
+        }
         free_ws(g_ws[d]);
     }
     (void)hipSetDevice(cur);
@@ -509,7 +985,7 @@ void mp_release(void)
 
 void mp_set_profiling(int on)
 {
-    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     for (auto &es : g_prof.pending) {
         for (int k = 0; k < 4; ++k) (void)hipEventDestroy(es.ev[k]);
         (void)hipHostFree(es.fb_host);
@@ -522,7 +998,7 @@ void mp_set_profiling(int on)
 int mp_profile_read(mp_stats *out)
 {
     if (!out) return fail(MP_EINVAL, "null pointer argument");
-    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
     for (auto &es : g_prof.pending) {
         float a = 0.f, b = 0.f, c = 0.f;
         HIP_TRY(hipEventSynchronize(es.ev[3]), "hipEventSynchronize");

@@ -70,23 +70,25 @@ __device__ __forceinline__ bool legal_pair(const Series &s, int64_t i, int64_t j
     return true;
 }
 
-// Queue row i for the exact search, seeded with its best known (key, distance).
-__device__ __forceinline__ void enqueue(const Fallback &fb, int64_t i, unsigned long long seed,
-                                        double ub)
+// Queue row i of job jb for the exact search, seeded with its best known
+// (key, distance).
+__device__ __forceinline__ void enqueue(const Fallback &fb, int32_t jb, int64_t i,
+                                        unsigned long long seed, double ub)
 {
     const int pos = atomicAdd(fb.count, 1);
     if (pos < fb.capacity) {
         fb.rows[pos] = (int32_t)i;
+        fb.job[pos] = jb;
         fb.keys[pos] = seed;
         fb.ub[pos] = ub;
     }
+    fb.job_flag[jb] = 1;
 }
 
 template <int KIND, int PC>
-__global__ void k_finalize(Series s, Fallback fb, double *P, int64_t *I)
+__device__ __forceinline__ void finalize_row(const Series &s, const Fallback &fb, int32_t jb,
+                                             int64_t i, double *P, int64_t *I)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.N) return;
     const unsigned long long mask = (1ull << s.gb) - 1ull;
     const unsigned long long key = s.keys[i];
     if ((KIND == ACAMP && s.isconst[i]) || key == KEY_NONE) {
@@ -96,15 +98,15 @@ __global__ void k_finalize(Series s, Fallback fb, double *P, int64_t *I)
     }
     const int64_t j = (int64_t)(key & mask);
     if (!legal_pair(s, i, j)) {
-        enqueue(fb, i, KEY_NONE, __longlong_as_double(0x7FF0000000000000ll));
+        enqueue(fb, jb, i, KEY_NONE, __longlong_as_double(0x7FF0000000000000ll));
         return;
     }
     const double ex = exact_sum<KIND, PC>(s, i, j);
     if (s.force_fb) {
         if (s.force_fb == 1)
-            enqueue(fb, i, pack_key(ex, (unsigned long long)j, mask), root_of<KIND, PC>(ex, s.p));
+            enqueue(fb, jb, i, pack_key(ex, (unsigned long long)j, mask), root_of<KIND, PC>(ex, s.p));
         else
-            enqueue(fb, i, KEY_NONE, __longlong_as_double(0x7FF0000000000000ll));
+            enqueue(fb, jb, i, KEY_NONE, __longlong_as_double(0x7FF0000000000000ll));
         return;
     }
     if (s.fp32) {
@@ -121,12 +123,28 @@ __global__ void k_finalize(Series s, Fallback fb, double *P, int64_t *I)
                            (KIND == ACAMP ? FP32_SELF_CHECK_ABS_Z : 0.0);
         // A winner at exact distance 0 is a minimum whatever the drift.
         if (ex != 0.0 && !(fabs(kv - xv) <= tol)) {
-            enqueue(fb, i, pack_key(ex, (unsigned long long)j, mask), root_of<KIND, PC>(ex, s.p));
+            enqueue(fb, jb, i, pack_key(ex, (unsigned long long)j, mask), root_of<KIND, PC>(ex, s.p));
             return;
         }
     }
     P[i] = root_of<KIND, PC>(ex, s.p);
     I[i] = j;
+}
+
+// Grid: x over windows, y over jobs.
+__global__ void k_finalize(Batch b)
+{
+    const int32_t jb = blockIdx.y;
+    const Job J = load_uniform(&b.jobs[jb]);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= J.s.N) return;
+    switch (sel_of(J.s.kind, J.s.pclass)) {
+    case SEL_AAMP: finalize_row<AAMP, P_TWO>(J.s, b.fb, jb, i, J.P, J.I); break;
+    case SEL_ACAMP: finalize_row<ACAMP, P_TWO>(J.s, b.fb, jb, i, J.P, J.I); break;
+    case SEL_P1: finalize_row<PNORM, P_ONE>(J.s, b.fb, jb, i, J.P, J.I); break;
+    case SEL_P3: finalize_row<PNORM, P_THREE>(J.s, b.fb, jb, i, J.P, J.I); break;
+    default: finalize_row<PNORM, P_GENERIC>(J.s, b.fb, jb, i, J.P, J.I); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -152,9 +170,12 @@ constexpr double FB_PD_SLACK = 2.5e-7;
 
 // Pivot windows spread evenly over the series; ACAMP skips constant windows
 // (looking up to 4096 windows ahead, else the pivot is left unused).
-__global__ void k_pick_pivots(Series s, Fallback fb)
+__global__ void k_pick_pivots(Batch b)
 {
-    if (*fb.count == 0) return;
+    const Fallback &fb = b.fb;
+    const int32_t jb = blockIdx.x;
+    if (fb.job_flag[jb] == 0) return;
+    const Series s = load_uniform(&b.jobs[jb]).s;
     const int lane = threadIdx.x;
     for (int k = 0; k < FB_PIVOTS; ++k) {
         const int64_t c0 = ((2 * (int64_t)k + 1) * s.N) / (2 * FB_PIVOTS);
@@ -168,21 +189,37 @@ __global__ void k_pick_pivots(Series s, Fallback fb)
                 found = (c0 + (int64_t)t * FB_WAVE + first) % s.N;
             }
         }
-        if (lane == 0) fb.pivots[k] = (int32_t)found;
+        if (lane == 0) fb.pivots[jb * FB_PIVOTS + k] = (int32_t)found;
     }
 }
 
 template <int KIND, int PC>
-__global__ void __launch_bounds__(256) k_pivot_dist(Series s, Fallback fb)
+__device__ __forceinline__ float pivot_distance(const Series &s, int32_t c, int64_t j)
 {
-    if (*fb.count == 0) return;
+    return c < 0 ? 0.0f : (float)root_of<KIND, PC>(exact_sum<KIND, PC>(s, c, j), s.p);
+}
+
+// Grid: x over windows, y over pivots, z over jobs.
+__global__ void __launch_bounds__(256) k_pivot_dist(Batch b)
+{
+    const Fallback &fb = b.fb;
+    const int32_t jb = blockIdx.z;
+    if (fb.job_flag[jb] == 0) return;
+    const Job J = load_uniform(&b.jobs[jb]);
+    const Series &s = J.s;
     const int k = blockIdx.y;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= s.N) return;
-    const int32_t c = fb.pivots[k];
-    float d = 0.0f;
-    if (c >= 0) d = (float)root_of<KIND, PC>(exact_sum<KIND, PC>(s, c, j), s.p);
-    fb.pd[(int64_t)k * fb.pd_stride + j] = d;
+    const int32_t c = fb.pivots[jb * FB_PIVOTS + k];
+    float d;
+    switch (sel_of(s.kind, s.pclass)) {
+    case SEL_AAMP: d = pivot_distance<AAMP, P_TWO>(s, c, j); break;
+    case SEL_ACAMP: d = pivot_distance<ACAMP, P_TWO>(s, c, j); break;
+    case SEL_P1: d = pivot_distance<PNORM, P_ONE>(s, c, j); break;
+    case SEL_P3: d = pivot_distance<PNORM, P_THREE>(s, c, j); break;
+    default: d = pivot_distance<PNORM, P_GENERIC>(s, c, j); break;
+    }
+    fb.pd[(int64_t)k * fb.pd_stride + J.key_base + j] = d;
 }
 
 __device__ __forceinline__ int lanes_below(unsigned long long mask)
@@ -191,32 +228,30 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// One work unit of the exact search: queue entry r (row i of the job whose
+// series is s), columns [c FB_CHUNK, (c + 1) FB_CHUNK). q is the LDS copy of
+// the row window (centred and scaled for ACAMP), staged when the row changes;
+// queue is the wave's candidate list.
 template <int KIND, int PC>
-__global__ void __launch_bounds__(FB_WAVE) k_fallback_scan(Series s, Fallback fb)
+__device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, int64_t pd_base,
+                                          const int32_t *pivots, int r, int64_t c, double *q,
+                                          int32_t *queue, int64_t &prev_row)
 {
-    __shared__ double q[FB_MAXM];
-    __shared__ int32_t queue[2 * FB_WAVE];
     const int lane = threadIdx.x;
-    const int cnt = min(*fb.count, fb.capacity);
-    const int64_t nch = (s.N + FB_CHUNK - 1) / FB_CHUNK;
-    const int64_t units = (int64_t)cnt * nch;
     const unsigned long long mask = (1ull << s.gb) - 1ull;
     const int m = s.m;
     const bool staged = m <= FB_MAXM;
-    int64_t prev_row = -1;
-    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int r = (int)(u / nch);
-        const int64_t c = u - (int64_t)r * nch;
+    {
         const int64_t i = fb.rows[r];
         const double thr = fb.ub[r] * (1.0 + 1e-9);
         const double mi = (KIND == ACAMP) ? s.mu[i] : 0.0;
         const double ni = (KIND == ACAMP) ? s.invn[i] : 1.0;
-        if (staged && i != prev_row) {
+        if (staged && (int64_t)r != prev_row) {
             __syncthreads();
             for (int l = lane; l < m; l += FB_WAVE)
                 q[l] = (KIND == ACAMP) ? (s.T[i + l] - mi) * ni : s.T[i + l];
             __syncthreads();
-            prev_row = i;
+            prev_row = r;
         }
         unsigned long long best = KEY_NONE;
         int qn = 0;
@@ -260,11 +295,11 @@ __global__ void __launch_bounds__(FB_WAVE) k_fallback_scan(Series s, Fallback fb
             bool cand = legal_pair(s, i, j);
             for (int k = 0; k < FB_PIVOTS; ++k) {
                 if (__ballot(cand) == 0) break;
-                if (fb.pivots[k] < 0) continue;
+                if (pivots[k] < 0) continue;
                 // the row's own pivot distance is uniform across the wavefront
-                const float pa = fb.pd[(int64_t)k * fb.pd_stride + i];
+                const float pa = fb.pd[(int64_t)k * fb.pd_stride + pd_base + i];
                 if (cand) {
-                    const double a = pa, b = fb.pd[(int64_t)k * fb.pd_stride + j];
+                    const double a = pa, b = fb.pd[(int64_t)k * fb.pd_stride + pd_base + j];
                     const double lb = fabs(a - b) - FB_PD_SLACK * (a + b);
                     if (lb > thr) cand = false;       // false for NaN bounds: kept
                 }
@@ -293,62 +328,88 @@ __global__ void __launch_bounds__(FB_WAVE) k_fallback_scan(Series s, Fallback fb
     }
 }
 
-// Rows of the fallback queue: decode the exact search's winner and rescore it.
-template <int KIND, int PC>
-__global__ void k_fallback_finish(Series s, Fallback fb, double *P, int64_t *I)
+// Grid-stride over the work units (queue entry, column chunk); chunks past
+// the entry's series end return at once.
+__global__ void __launch_bounds__(FB_WAVE) k_fallback_scan(Batch b)
 {
+    __shared__ double q[FB_MAXM];
+    __shared__ int32_t queue[2 * FB_WAVE];
+    const Fallback &fb = b.fb;
     const int cnt = min(*fb.count, fb.capacity);
-    const unsigned long long mask = (1ull << s.gb) - 1ull;
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < cnt; r += gridDim.x * blockDim.x) {
-        const int64_t i = fb.rows[r];
-        const unsigned long long key = fb.keys[r];
-        if (key == KEY_NONE) {
-            P[i] = __longlong_as_double(0x7FF0000000000000ll);
-            I[i] = -1;
-        } else {
-            const int64_t j = (int64_t)(key & mask);
-            P[i] = root_of<KIND, PC>(exact_sum<KIND, PC>(s, i, j), s.p);
-            I[i] = j;
+    const int64_t nch = (b.max_N + FB_CHUNK - 1) / FB_CHUNK;
+    const int64_t units = (int64_t)cnt * nch;
+    int64_t prev_row = -1;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int r = (int)(u / nch);
+        const int64_t c = u - (int64_t)r * nch;
+        const int32_t jb = __builtin_amdgcn_readfirstlane(fb.job[r]);
+        const Job J = load_uniform(&b.jobs[jb]);
+        const Series &s = J.s;
+        if (c * FB_CHUNK >= s.N) continue;
+        const int32_t *piv = fb.pivots + jb * FB_PIVOTS;
+        switch (sel_of(s.kind, s.pclass)) {
+        case SEL_AAMP: scan_unit<AAMP, P_TWO>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
+        case SEL_ACAMP: scan_unit<ACAMP, P_TWO>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
+        case SEL_P1: scan_unit<PNORM, P_ONE>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
+        case SEL_P3: scan_unit<PNORM, P_THREE>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
+        default: scan_unit<PNORM, P_GENERIC>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
         }
     }
 }
 
-hipError_t launch_finalize(const Series &s, const Fallback &fb, double *P, int64_t *I,
-                           hipStream_t st)
+// Rows of the fallback queue: decode the exact search's winner and rescore it.
+template <int KIND, int PC>
+__device__ __forceinline__ void finish_row(const Job &J, unsigned long long key, int64_t i)
 {
+    const Series &s = J.s;
+    const unsigned long long mask = (1ull << s.gb) - 1ull;
+    if (key == KEY_NONE) {
+        J.P[i] = __longlong_as_double(0x7FF0000000000000ll);
+        J.I[i] = -1;
+    } else {
+        const int64_t j = (int64_t)(key & mask);
+        J.P[i] = root_of<KIND, PC>(exact_sum<KIND, PC>(s, i, j), s.p);
+        J.I[i] = j;
+    }
+}
+
+__global__ void k_fallback_finish(Batch b)
+{
+    const Fallback &fb = b.fb;
+    const int cnt = min(*fb.count, fb.capacity);
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < cnt; r += gridDim.x * blockDim.x) {
+        const Job J = b.jobs[fb.job[r]];
+        const int64_t i = fb.rows[r];
+        const unsigned long long key = fb.keys[r];
+        switch (sel_of(J.s.kind, J.s.pclass)) {
+        case SEL_AAMP: finish_row<AAMP, P_TWO>(J, key, i); break;
+        case SEL_ACAMP: finish_row<ACAMP, P_TWO>(J, key, i); break;
+        case SEL_P1: finish_row<PNORM, P_ONE>(J, key, i); break;
+        case SEL_P3: finish_row<PNORM, P_THREE>(J, key, i); break;
+        default: finish_row<PNORM, P_GENERIC>(J, key, i); break;
+        }
+    }
+}
+
+hipError_t launch_finalize(const Batch &b, hipStream_t st)
+{
+    if (b.njobs <= 0) return hipSuccess;
     const int B = 256;
-    dim3 g((unsigned)((s.N + B - 1) / B));
-    if (s.kind == AAMP)
-        hipLaunchKernelGGL((k_finalize<AAMP, P_TWO>), g, dim3(B), 0, st, s, fb, P, I);
-    else if (s.kind == ACAMP)
-        hipLaunchKernelGGL((k_finalize<ACAMP, P_TWO>), g, dim3(B), 0, st, s, fb, P, I);
-    else if (s.pclass == P_ONE)
-        hipLaunchKernelGGL((k_finalize<PNORM, P_ONE>), g, dim3(B), 0, st, s, fb, P, I);
-    else if (s.pclass == P_THREE)
-        hipLaunchKernelGGL((k_finalize<PNORM, P_THREE>), g, dim3(B), 0, st, s, fb, P, I);
-    else
-        hipLaunchKernelGGL((k_finalize<PNORM, P_GENERIC>), g, dim3(B), 0, st, s, fb, P, I);
+    dim3 g((unsigned)((b.max_N + B - 1) / B), (unsigned)b.njobs);
+    hipLaunchKernelGGL(k_finalize, g, dim3(B), 0, st, b);
     return hipGetLastError();
 }
 
-hipError_t launch_fallback(const Series &s, const Fallback &fb, double *P, int64_t *I,
-                           hipStream_t st)
+hipError_t launch_fallback(const Batch &b, hipStream_t st)
 {
-    // Every kernel returns at once when the queue is empty.
-    const dim3 gpd((unsigned)((s.N + 255) / 256), FB_PIVOTS);
-    hipLaunchKernelGGL(k_pick_pivots, dim3(1), dim3(FB_WAVE), 0, st, s, fb);
-#define MP_FB(K, PCL)                                                                   \
-    do {                                                                                \
-        hipLaunchKernelGGL((k_pivot_dist<K, PCL>), gpd, dim3(256), 0, st, s, fb);         \
-        hipLaunchKernelGGL((k_fallback_scan<K, PCL>), dim3(8192), dim3(FB_WAVE), 0, st, s, fb); \
-        hipLaunchKernelGGL((k_fallback_finish<K, PCL>), dim3(64), dim3(256), 0, st, s, fb, P, I); \
-    } while (0)
-    if (s.kind == AAMP) MP_FB(AAMP, P_TWO);
-    else if (s.kind == ACAMP) MP_FB(ACAMP, P_TWO);
-    else if (s.pclass == P_ONE) MP_FB(PNORM, P_ONE);
-    else if (s.pclass == P_THREE) MP_FB(PNORM, P_THREE);
-    else MP_FB(PNORM, P_GENERIC);
-#undef MP_FB
+    // Every kernel returns at once when the queue (or the job's share of it)
+    // is empty.
+    if (b.njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pick_pivots, dim3((unsigned)b.njobs), dim3(FB_WAVE), 0, st, b);
+    const dim3 gpd((unsigned)((b.max_N + 255) / 256), FB_PIVOTS, (unsigned)b.njobs);
+    hipLaunchKernelGGL(k_pivot_dist, gpd, dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_fallback_scan, dim3(8192), dim3(FB_WAVE), 0, st, b);
+    hipLaunchKernelGGL(k_fallback_finish, dim3(64), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

@@ -12,8 +12,10 @@ namespace mpk {
 // window (no running sums, so no cancellation over long series). A constant
 // window gets invn = 0; its z-normalized distance to anything is infinite
 // (Sec. 1) and the sweep never lets it win.
-__global__ void k_window_stats(Series s)
+__global__ void k_window_stats(Batch b)
 {
+    const Series s = load_uniform(&b.jobs[blockIdx.y]).s;
+    if (s.kind != ACAMP) return;
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= s.N) return;
     const double *w = s.T + j;
@@ -52,13 +54,18 @@ __global__ void k_window_stats(Series s)
 //        dg_j = (t_{j+m-1} - mu_j) + (t_{j-1} - mu_{j-1}).
 //        Stored with z_j = -invn_j so that -rho = cov invn_i z_j.
 // Entries j >= N hold sentinels that make every pair touching them lose.
-__global__ void k_streams(Series s)
+// Also resets the launch's exact-search queue and the job's queue flag.
+__global__ void k_streams(Batch b)
 {
+    const Series s = load_uniform(&b.jobs[blockIdx.y]).s;
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = s.N + STREAM_PAD;
     if (j >= total) return;
     if (j < s.N) s.keys[j] = KEY_NONE;
-    if (j == 0) *s.fb_count = 0;
+    if (j == 0) {
+        b.fb.job_flag[blockIdx.y] = 0;
+        if (blockIdx.y == 0) *b.fb.count = 0;
+    }
     const int m = s.m;
     double x = 0.0, y = 0.0, z = 0.0;
     if (j >= s.N) {
@@ -124,17 +131,33 @@ __global__ void k_streams(Series s)
     }
 }
 
-hipError_t launch_prep(const Series &s, hipStream_t st)
+// Job table of a single-series call, written on the stream from the kernel
+// arguments so that consecutive calls never share a host staging buffer.
+__global__ void k_store_job(Job j, RowBase4 rb, Job *dst, int64_t *row_base)
+{
+    if (threadIdx.x == 0) *dst = j;
+    if (threadIdx.x < rb.count) row_base[threadIdx.x] = rb.v[threadIdx.x];
+}
+
+hipError_t launch_store_job(const Job &j, const RowBase4 &rb, Job *dst, int64_t *row_base,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_store_job, dim3(1), dim3(64), 0, st, j, rb, dst, row_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const Batch &b, uint32_t sels, hipStream_t st)
 {
     const int B = 256;
-    if (s.kind == ACAMP) {
-        unsigned g = (unsigned)((s.N + B - 1) / B);
-        hipLaunchKernelGGL(k_window_stats, dim3(g), dim3(B), 0, st, s);
+    if (b.njobs <= 0) return hipSuccess;
+    if (sels & SEL_ACAMP) {
+        dim3 g((unsigned)((b.max_N + B - 1) / B), (unsigned)b.njobs);
+        hipLaunchKernelGGL(k_window_stats, g, dim3(B), 0, st, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    unsigned g = (unsigned)((s.N + STREAM_PAD + B - 1) / B);
-    hipLaunchKernelGGL(k_streams, dim3(g), dim3(B), 0, st, s);
+    dim3 g((unsigned)((b.max_stream + B - 1) / B), (unsigned)b.njobs);
+    hipLaunchKernelGGL(k_streams, g, dim3(B), 0, st, b);
     return hipGetLastError();
 }
 

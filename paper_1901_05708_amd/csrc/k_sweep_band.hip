@@ -219,16 +219,15 @@ struct Streams<float> {
 
 }  // namespace
 
+// One work item: the diagonals [k_lo, k_lo + 64 KD) of series s, rows
+// [i0, i1). ring (NF x RING entries) and rowbuf (NRB x 64) are the wave's LDS.
 template <int KIND, int PC, int KD, typename F>
-__global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
+__device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, const int64_t i0,
+                                          const int64_t i1, F *ring, F *rowbuf)
 {
     typedef Prec<F> P;
     constexpr int WD = 64 * KD;          // diagonals per item
     constexpr int RING = WD;             // ring entries per field
-    constexpr int NF = (KIND == ACAMP) ? 3 : 2;
-
-    __shared__ F ring[NF][RING];
-    __shared__ F rowbuf[NRB * 64];
 
     const int lane = threadIdx.x;
     const int64_t N = s.N;
@@ -244,38 +243,11 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
     const F *sx = Streams<F>::x(s);
     const F *sy = Streams<F>::y(s);
     const F *sz = Streams<F>::z(s);
-    cint64 *band_start = as_const(bp.band_start);
-    const int64_t total = band_start[bp.nbands];   // rows summed over all bands
     cdouble *Tc = as_const(s.T);
     const auto xc = as_const(sx);
     const auto yc = as_const(sy);
     const auto zc = as_const(sz);
-
-    // This wave's share of the band-major row space: every row of a band costs
-    // the same (pairs past the series end run on sentinels), so equal row
-    // ranges are equal work. share = total / G rows, the first total % G waves
-    // take one more.
-    const int64_t G = gridDim.x;
-    const int64_t w = blockIdx.x;
-    const int64_t qrows = total / G, rrows = total % G;
-    int64_t pos = uniform64(w * qrows + min(w, rrows));
-    const int64_t pend = uniform64(pos + qrows + (w < rrows ? 1 : 0));
-
-    while (pos < pend) {
-        // band holding row position pos: band_start[b] <= pos < band_start[b + 1]
-        int lo = 0, hi = bp.nbands;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (band_start[mid] <= pos) lo = mid;
-            else hi = mid;
-        }
-        // one item: rows of band lo from pos up to the end of the range, the
-        // band, or the refresh interval, whichever comes first
-        const int64_t k_lo = uniform64((int64_t)s.excl + (int64_t)lo * WD);
-        const int64_t seg = uniform64(min(min(pend, band_start[lo + 1]), pos + (int64_t)bp.seg_rows) - pos);
-        const int64_t i0 = uniform64(pos - band_start[lo]);
-        const int64_t i1 = i0 + seg;
-        pos += seg;
+    {
         const int nsteps = (int)(i1 - i0) - 1;      // recurrence steps after the first row
         const int64_t cb = i0 + k_lo;               // stream index of local column 0
 
@@ -329,9 +301,9 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         for (int q = 0; q < RING / 64; ++q) {
             const int c = lane + 64 * q;
             const int e = ring_pos<KD>(c);
-            ring[0][e] = sx[cb + c];
-            ring[1][e] = sy[cb + c];
-            if (KIND == ACAMP) ring[2][e] = sz[cb + c];
+            ring[e] = sx[cb + c];
+            ring[RING + e] = sy[cb + c];
+            if (KIND == ACAMP) ring[2 * RING + e] = sz[cb + c];
         }
         lds_order();
 
@@ -348,9 +320,9 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
         for (int d = 0; d < KD - 1; ++d) {
             const int c = KD * lane + 1 + d;
             const int e = ring_pos<KD>(c);
-            cx[(1 + d) % KD] = ring[0][e];
-            cy[(1 + d) % KD] = ring[1][e];
-            if (KIND == ACAMP) cz[(1 + d) % KD] = ring[2][e];
+            cx[(1 + d) % KD] = ring[e];
+            cy[(1 + d) % KD] = ring[RING + e];
+            if (KIND == ACAMP) cz[(1 + d) % KD] = ring[2 * RING + e];
         }
 
         F colacc[KD];
@@ -460,9 +432,9 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
             lds_order();
             if (lane < KD) {
                 const int e = ring_pos<KD>((tb + RING + lane) & (RING - 1));
-                ring[0][e] = bx;
-                ring[1][e] = by;
-                if (KIND == ACAMP) ring[2][e] = bz;
+                ring[e] = bx;
+                ring[RING + e] = by;
+                if (KIND == ACAMP) ring[2 * RING + e] = bz;
             }
             lds_order();
             {
@@ -480,9 +452,9 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
                 const int tau = tb + q;
                 {
                     const int e = ebase ^ q;
-                    cx[q] = ring[0][e];
-                    cy[q] = ring[1][e];
-                    if (KIND == ACAMP) cz[q] = ring[2][e];
+                    cx[q] = ring[e];
+                    cy[q] = ring[RING + e];
+                    if (KIND == ACAMP) cz[q] = ring[2 * RING + e];
                 }
                 const F rx = rxs[q];
                 const F ry = rys[q];
@@ -541,97 +513,152 @@ __global__ void __launch_bounds__(64) k_sweep_band(Series s, BandPlan bp)
     }
 }
 
-// Prefix sums of the rows of each band. Band b covers diagonals
-// [excl + b W, excl + (b+1) W); its longest diagonal has N - excl - b W rows.
-__global__ void __launch_bounds__(1024) k_band_plan(int64_t N, int32_t excl, BandPlan bp)
+// The persistent sweep over every band of every job of a launch. SELS is the
+// set of distance specialisations the launch holds: a single one gets a kernel
+// of its own; a mix dispatches per item (the branch is wave-uniform).
+template <uint32_t SELS, int KD, typename F>
+__global__ void __launch_bounds__(64) k_sweep_band(Batch b)
+{
+    constexpr int RING = 64 * KD;
+    constexpr int NF = (SELS & SEL_ACAMP) ? 3 : 2;
+    __shared__ F ring[NF * RING];
+    __shared__ F rowbuf[NRB * 64];
+
+    cint64 *row_base = as_const(b.row_base);
+    cint64 *band_start = as_const(b.band_start);
+    const int64_t total = row_base[b.njobs];   // band-row positions of the launch
+
+    // This wave's share of the band-row space: every row of a band costs the
+    // same (pairs past the series end run on sentinels), so equal row ranges
+    // are nearly equal work. share = total / G rows, the first total % G waves
+    // take one more.
+    const int64_t G = gridDim.x;
+    const int64_t w = blockIdx.x;
+    const int64_t qrows = total / G, rrows = total % G;
+    int64_t pos = uniform64(w * qrows + min(w, rrows));
+    const int64_t pend = uniform64(pos + qrows + (w < rrows ? 1 : 0));
+
+    while (pos < pend) {
+        // job holding position pos: the last job with row_base <= pos (jobs
+        // without band rows share their successor's row_base and are skipped)
+        int jlo = 0, jhi = b.njobs;
+        while (jhi - jlo > 1) {
+            const int mid = (jlo + jhi) >> 1;
+            if (row_base[mid] <= pos) jlo = mid;
+            else jhi = mid;
+        }
+        jlo = __builtin_amdgcn_readfirstlane(jlo);
+        const Job J = load_uniform(&b.jobs[jlo]);
+        const Series &s = J.s;
+        cint64 *bs = band_start + J.band_base;
+        // band of the job holding pos: bs[t] <= pos < bs[t + 1]
+        int lo = 0, hi = J.nbands;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bs[mid] <= pos) lo = mid;
+            else hi = mid;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        // one item: rows of band lo from pos up to the end of the share, the
+        // band, or the refresh interval, whichever comes first
+        const int64_t k_lo = uniform64((int64_t)s.excl + (int64_t)lo * RING);
+        const int64_t seg = uniform64(min(min(pend, bs[lo + 1]), pos + (int64_t)J.seg_rows) - pos);
+        const int64_t i0 = uniform64(pos - bs[lo]);
+        pos += seg;
+        const uint32_t sel = sel_of(s.kind, s.pclass);
+        if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
+            band_item<AAMP, P_TWO, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+        else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
+            band_item<ACAMP, P_TWO, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+        else if ((SELS & SEL_P1) && sel == SEL_P1)
+            band_item<PNORM, P_ONE, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+        else if ((SELS & SEL_P3) && sel == SEL_P3)
+            band_item<PNORM, P_THREE, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+    }
+}
+
+// Band table of every job (one block per job): bs[t] = row_base of the job +
+// rows of its bands before t, where band t has N - excl - t W rows; the last
+// entry bs[nbands] is the job's end.
+__global__ void __launch_bounds__(1024) k_band_plan(Batch b)
 {
     __shared__ int64_t part[1024];
+    const Job J = load_uniform(&b.jobs[blockIdx.x]);
+    const int64_t base = J.row_start;
+    const int64_t N = J.s.N, excl = J.s.excl, W = b.band_width;
+    const int nb = J.nbands;
+    int64_t *bs = b.band_start + J.band_base;
     const int t = threadIdx.x;
-    const int nb = bp.nbands;
     const int per = (nb + 1023) / 1024;
     const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
     int64_t sum = 0;
-    for (int b = b0; b < b1; ++b) sum += N - excl - (int64_t)b * bp.band_width;
+    for (int u = b0; u < b1; ++u) sum += N - excl - (int64_t)u * W;
     part[t] = sum;
     __syncthreads();
     if (t == 0) {
-        int64_t run = 0;
+        int64_t run = base;
         for (int u = 0; u < 1024; ++u) {
-            int64_t v = part[u];
+            const int64_t v = part[u];
             part[u] = run;
             run += v;
         }
-        bp.band_start[nb] = run;
+        bs[nb] = run;
     }
     __syncthreads();
     int64_t run = part[t];
-    for (int b = b0; b < b1; ++b) {
-        bp.band_start[b] = run;
-        run += N - excl - (int64_t)b * bp.band_width;
+    for (int u = b0; u < b1; ++u) {
+        bs[u] = run;
+        run += N - excl - (int64_t)u * W;
     }
 }
 
-hipError_t launch_plan(const Series &s, const BandPlan &bp, hipStream_t st)
+hipError_t launch_plan(const Batch &b, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_band_plan, dim3(1), dim3(1024), 0, st, s.N, s.excl, bp);
+    if (b.njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_band_plan, dim3((unsigned)b.njobs), dim3(1024), 0, st, b);
     return hipGetLastError();
 }
 
+namespace {
+
+// Kernel of a selector set: one of its own for a single specialisation,
+// otherwise the mixed kernel holding all band specialisations.
 template <int KD, typename F>
-static hipError_t launch_kd(const Series &s, const BandPlan &bp, int32_t grid, hipStream_t st)
+const void *band_kernel(uint32_t sels)
 {
-    if (s.kind == AAMP)
-        hipLaunchKernelGGL((k_sweep_band<AAMP, P_TWO, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
-    else if (s.kind == ACAMP)
-        hipLaunchKernelGGL((k_sweep_band<ACAMP, P_TWO, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
-    else if (s.pclass == P_ONE)
-        hipLaunchKernelGGL((k_sweep_band<PNORM, P_ONE, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
-    else if (s.pclass == P_THREE)
-        hipLaunchKernelGGL((k_sweep_band<PNORM, P_THREE, KD, F>), dim3(grid), dim3(64), 0, st, s, bp);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    switch (sels & SEL_BAND) {
+    case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP, KD, F>;
+    case SEL_ACAMP: return (const void *)k_sweep_band<SEL_ACAMP, KD, F>;
+    case SEL_P1: return (const void *)k_sweep_band<SEL_P1, KD, F>;
+    case SEL_P3: return (const void *)k_sweep_band<SEL_P3, KD, F>;
+    default: return (const void *)k_sweep_band<SEL_BAND, KD, F>;
+    }
 }
 
-hipError_t launch_sweep_band(const Series &s, const BandPlan &bp, int32_t diags_per_lane,
+const void *band_kernel_for(uint32_t sels, int32_t kd, bool fp32)
+{
+    if (fp32) return kd == 16 ? band_kernel<16, float>(sels) : band_kernel<8, float>(sels);
+    return band_kernel<8, double>(sels);
+}
+
+}  // namespace
+
+hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_lane, bool fp32,
                              int32_t grid, hipStream_t st)
 {
-    if (s.fp32) {
-        if (diags_per_lane == 8) return launch_kd<8, float>(s, bp, grid, st);
-        if (diags_per_lane == 16) return launch_kd<16, float>(s, bp, grid, st);
-    } else {
-        if (diags_per_lane == 8) return launch_kd<8, double>(s, bp, grid, st);
-        if (diags_per_lane == 16) return launch_kd<16, double>(s, bp, grid, st);
-    }
-    return hipErrorInvalidValue;
+    if (grid <= 0 || !(sels & SEL_BAND)) return hipSuccess;
+    const void *k = band_kernel_for(sels, diags_per_lane, fp32);
+    Batch arg = b;
+    void *args[] = {&arg};
+    return hipLaunchKernel(k, dim3(grid), dim3(64), args, 0, st);
 }
 
-template <int KD, typename F>
-static int32_t occupancy_kd(const Series &s)
+int32_t band_blocks_per_cu(uint32_t sels, int32_t diags_per_lane, bool fp32)
 {
     int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    if (s.kind == AAMP)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<AAMP, P_TWO, KD, F>, 64, 0);
-    else if (s.kind == ACAMP)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<ACAMP, P_TWO, KD, F>, 64, 0);
-    else if (s.pclass == P_ONE)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_ONE, KD, F>, 64, 0);
-    else if (s.pclass == P_THREE)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sweep_band<PNORM, P_THREE, KD, F>, 64, 0);
+    const void *k = band_kernel_for(sels, diags_per_lane, fp32);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
-}
-
-int32_t band_blocks_per_cu(const Series &s, int32_t diags_per_lane)
-{
-    if (s.fp32) return diags_per_lane == 16 ? occupancy_kd<16, float>(s) : occupancy_kd<8, float>(s);
-    return diags_per_lane == 16 ? occupancy_kd<16, double>(s) : occupancy_kd<8, double>(s);
-}
-
-int32_t band_lds_bytes(int32_t kind, int32_t diags_per_lane)
-{
-    const int nf = kind == ACAMP ? 3 : 2;
-    return (int32_t)(8 * (nf * 64 * diags_per_lane + NRB * 64));
 }
 
 }  // namespace mpk

@@ -22,7 +22,7 @@ __device__ __forceinline__ double pnorm_term(double d, double p)
 }
 
 template <int KIND, int PC>
-__global__ void k_sweep_simple(Series s, int32_t R)
+__device__ __forceinline__ void sweep_simple(const Series &s, int32_t R)
 {
     const int64_t k = (int64_t)s.excl + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= s.N) return;
@@ -72,24 +72,29 @@ __global__ void k_sweep_simple(Series s, int32_t R)
     }
 }
 
-hipError_t launch_sweep_simple(const Series &s, int32_t R, hipStream_t st)
+// Grid: x over diagonals, y over row segments, z over jobs; jobs of the band
+// kernel (nbands > 0) return at once.
+__global__ void k_sweep_simple(Batch b)
 {
-    const int64_t ndiag = s.N - s.excl;
-    if (ndiag <= 0) return hipSuccess;
-    const int B = 256;
-    const int64_t nseg = (ndiag + R - 1) / R;
-    dim3 grid((unsigned)((ndiag + B - 1) / B), (unsigned)nseg);
-    if (s.kind == AAMP) {
-        hipLaunchKernelGGL((k_sweep_simple<AAMP, P_TWO>), grid, dim3(B), 0, st, s, R);
-    } else if (s.kind == ACAMP) {
-        hipLaunchKernelGGL((k_sweep_simple<ACAMP, P_TWO>), grid, dim3(B), 0, st, s, R);
-    } else if (s.pclass == P_ONE) {
-        hipLaunchKernelGGL((k_sweep_simple<PNORM, P_ONE>), grid, dim3(B), 0, st, s, R);
-    } else if (s.pclass == P_THREE) {
-        hipLaunchKernelGGL((k_sweep_simple<PNORM, P_THREE>), grid, dim3(B), 0, st, s, R);
-    } else {
-        hipLaunchKernelGGL((k_sweep_simple<PNORM, P_GENERIC>), grid, dim3(B), 0, st, s, R);
+    const Job J = load_uniform(&b.jobs[blockIdx.z]);
+    if (J.nbands > 0) return;
+    const Series s = J.s;
+    const int32_t R = J.seg_rows;
+    switch (sel_of(s.kind, s.pclass)) {
+    case SEL_AAMP: sweep_simple<AAMP, P_TWO>(s, R); break;
+    case SEL_ACAMP: sweep_simple<ACAMP, P_TWO>(s, R); break;
+    case SEL_P1: sweep_simple<PNORM, P_ONE>(s, R); break;
+    case SEL_P3: sweep_simple<PNORM, P_THREE>(s, R); break;
+    default: sweep_simple<PNORM, P_GENERIC>(s, R); break;
     }
+}
+
+hipError_t launch_sweep_simple(const Batch &b, hipStream_t st)
+{
+    if (b.simple_diag <= 0 || b.simple_segs <= 0 || b.njobs <= 0) return hipSuccess;
+    const int B = 256;
+    dim3 grid((unsigned)((b.simple_diag + B - 1) / B), (unsigned)b.simple_segs, (unsigned)b.njobs);
+    hipLaunchKernelGGL(k_sweep_simple, grid, dim3(B), 0, st, b);
     return hipGetLastError();
 }
 

@@ -57,8 +57,6 @@ struct Series {
     uint8_t *isconst;
     // Packed (value, index) keys, N entries; ~0 = no candidate.
     unsigned long long *keys;
-    // Fallback-queue counter, zeroed by the preparation kernel.
-    int32_t *fb_count;
     // FP32 copies of the streams (MP_FP32_REFRESH), recentred before rounding:
     //   AAMP:  xf = u_j, yf = v_j - 2c;  PNORM: xf = a_j - c, yf = b_j - c;
     //   ACAMP: xf = df_j, yf = dg_j, zf = -invn_j; c = t_0.
@@ -83,47 +81,111 @@ constexpr double FP32_SELF_CHECK_ABS_Z = 2.5e-7;
 // Pivot windows of the exact fallback search (triangle-inequality pruning).
 constexpr int FB_PIVOTS = 16;
 
-// Fallback list: rows whose winner must be recomputed exactly.
+// Exact-search queue, shared by the jobs of a launch: rows whose winner must
+// be recomputed exactly.
 struct Fallback {
-    int32_t *count;        // one counter
-    int32_t *rows;         // capacity entries
+    int32_t *count;        // one counter, zeroed by the preparation kernel
+    int32_t *rows;         // capacity entries: row within its job
+    int32_t *job;          // capacity entries: job of the row
     unsigned long long *keys;   // capacity entries: best (value, index) found so far
     double *ub;            // capacity entries: upper bound on the row's distance (+inf: none)
-    int32_t *pivots;       // FB_PIVOTS window indices (-1: unused)
-    float *pd;             // FB_PIVOTS x pd_stride: distance of every window to each pivot
+    int32_t *job_flag;     // per job: 1 once a row of the job is queued (zeroed by prep)
+    int32_t *pivots;       // FB_PIVOTS per job: window indices (-1: unused)
+    float *pd;             // FB_PIVOTS x pd_stride: distance of every window to each
+                           // pivot of its job; job b's windows start at its key_base
     int64_t pd_stride;
     int32_t capacity;
     int32_t pad0;
 };
 
-// Band-sweep work decomposition (computed on the device by launch_plan).
-struct BandPlan {
-    int32_t band_width;    // diagonals per band = 64 lanes x diagonals per lane
-    int32_t seg_rows;      // longest run of rows between exact restarts (refresh interval R)
-    int32_t nbands;
-    int32_t pad0;
-    int64_t *band_start;   // nbands + 1 prefix sums of the rows of each band
+// One series of a launch; a single-series call is a batch of one job.
+struct Job {
+    Series s;              // views of the job's slices of the workspace
+    double *P;             // N outputs
+    int64_t *I;
+    int64_t row_start;     // first band-row position of the job in its sweep's row space
+    int64_t band_base;     // first entry of the job's band table
+    int64_t key_base;      // offset of the job's windows in the launch's key space
+    int32_t nbands;        // bands of the band kernel (0: simple kernel, or no pairs)
+    int32_t seg_rows;      // rows between exact restarts (refresh interval R)
 };
 
-// --- launch wrappers (return the hipError_t of the launch) -------------------
-hipError_t launch_prep(const Series &s, hipStream_t st);
-hipError_t launch_sweep_simple(const Series &s, int32_t R, hipStream_t st);
-hipError_t launch_plan(const Series &s, const BandPlan &bp, hipStream_t st);
-hipError_t launch_sweep_band(const Series &s, const BandPlan &bp, int32_t diags_per_lane,
-                             int32_t grid, hipStream_t st);
-hipError_t launch_finalize(const Series &s, const Fallback &fb, double *P, int64_t *I,
-                           hipStream_t st);
-hipError_t launch_fallback(const Series &s, const Fallback &fb, double *P, int64_t *I,
-                           hipStream_t st);
+// Job tables are read-only during a launch: kernels read them through the
+// constant address space so that wave-uniform fields become scalar loads.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "dword-sized record");
+    typedef const __attribute__((address_space(4))) uint32_t cu32;
+    const cu32 *src = (const cu32 *)p;
+    T v;
+    uint32_t *dst = (uint32_t *)&v;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+    return v;
+}
 
-int32_t band_lds_bytes(int32_t kind, int32_t diags_per_lane);
-int32_t band_blocks_per_cu(const Series &s, int32_t diags_per_lane);
+// Everything a launch works on. Band-row positions: a band sweep's work is
+// the concatenation over its jobs of each job's bands (band t of a job covers
+// diagonals [excl + t W, excl + (t+1) W) and has N - excl - t W rows). A
+// launch holds up to two band sweeps (FP64 and FP32 jobs), each over a
+// contiguous range of the job table; a sweep sees a Batch restricted to its
+// range.
+struct Batch {
+    const Job *jobs;           // njobs entries
+    const int64_t *row_base;   // band sweeps: njobs + 1 row_start values, then the total
+    int64_t *band_start;       // per job nbands + 1 entries from band_base: launch positions
+    int32_t njobs;
+    int32_t band_width;        // 64 x diagonals per lane
+    int64_t max_N;             // largest N of the jobs (grid of per-window kernels)
+    int64_t max_stream;        // largest N + STREAM_PAD
+    int64_t simple_diag;       // largest diagonal count of the simple kernel's jobs
+    int64_t simple_segs;       // largest segment count of the simple kernel's jobs
+    Fallback fb;
+};
+
+// Kernel selectors: which distance specialisations a launch contains.
+enum Sel : uint32_t {
+    SEL_AAMP = 1,
+    SEL_ACAMP = 2,
+    SEL_P1 = 4,
+    SEL_P3 = 8,
+    SEL_PGEN = 16,
+};
+
+__host__ __device__ inline uint32_t sel_of(int32_t kind, int32_t pclass)
+{
+    if (kind == AAMP) return SEL_AAMP;
+    if (kind == ACAMP) return SEL_ACAMP;
+    if (pclass == P_ONE) return SEL_P1;
+    if (pclass == P_THREE) return SEL_P3;
+    return SEL_PGEN;
+}
 
 // Band kernels exist for AAMP, ACAMP and p-norm with p in {1, 3}; other p use
 // the simple kernel (the sentinel entries are only sized for those powers).
-inline bool band_supported(const Series &s)
-{
-    return s.kind == AAMP || s.kind == ACAMP || (s.kind == PNORM && (s.pclass == P_ONE || s.pclass == P_THREE));
-}
+constexpr uint32_t SEL_BAND = SEL_AAMP | SEL_ACAMP | SEL_P1 | SEL_P3;
+
+// --- launch wrappers (return the hipError_t of the launch) -------------------
+// The row_base table of a one-job launch (at most 3 entries: the two band
+// sweeps' prefixes, one of them empty).
+struct RowBase4 {
+    int64_t v[4];
+    int32_t count;
+    int32_t pad0;
+};
+hipError_t launch_store_job(const Job &j, const RowBase4 &rb, Job *dst, int64_t *row_base,
+                            hipStream_t st);
+hipError_t launch_prep(const Batch &b, uint32_t sels, hipStream_t st);
+hipError_t launch_plan(const Batch &b, hipStream_t st);
+hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_lane, bool fp32,
+                             int32_t grid, hipStream_t st);
+hipError_t launch_sweep_simple(const Batch &b, hipStream_t st);
+hipError_t launch_finalize(const Batch &b, hipStream_t st);
+hipError_t launch_fallback(const Batch &b, hipStream_t st);
+
+// Band-kernel facts for the planner: resident waves per CU for a selector set,
+// and the selector sets that have their own kernel (others use the mixed one).
+int32_t band_blocks_per_cu(uint32_t sels, int32_t diags_per_lane, bool fp32);
 
 }  // namespace mpk

@@ -65,6 +65,37 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.mp_batch(None, jobs, 1, 0, dummy, dummy, None) == mp.MP_EINVAL
 
 
+def test_batch_table_errors_rejected_without_gpu(lib):
+    dummy = ctypes.c_void_p(16)
+    ok = mp.MpJob(0, 100, 0, 10, mp.KIND_AAMP, 0, 0, 2.0)
+    # overlapping output ranges (91 outputs from 0, the second job starts at 50)
+    jobs = (mp.MpJob * 2)(ok, mp.MpJob(100, 100, 50, 10, mp.KIND_ACAMP, 0, 0, 2.0))
+    assert lib.mp_batch(dummy, jobs, 2, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert "overlap" in lib.mp_strerror(mp.MP_EINVAL).decode()
+    # negative offsets, bad m, bad p, too many jobs, bad precision
+    for bad in (mp.MpJob(-1, 100, 0, 10, 0, 0, 0, 2.0), mp.MpJob(0, 100, -5, 10, 0, 0, 0, 2.0),
+                mp.MpJob(0, 100, 0, 101, 0, 0, 0, 2.0), mp.MpJob(0, 100, 0, 10, 1, 0, 0, 0.9),
+                mp.MpJob(0, 100, 0, 10, 0, 0, -2, 2.0)):
+        jobs = (mp.MpJob * 1)(bad)
+        assert lib.mp_batch(dummy, jobs, 1, 0, dummy, dummy, None) == mp.MP_EINVAL
+    jobs = (mp.MpJob * 1)(ok)
+    assert lib.mp_batch(dummy, jobs, 65536, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_batch(dummy, jobs, -1, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_batch(dummy, jobs, 1, 3, dummy, dummy, None) == mp.MP_EINVAL
+    # an empty batch is a no-op that needs no device
+    assert lib.mp_batch(dummy, jobs, 0, 0, dummy, dummy, None) == mp.MP_OK
+
+
+def test_stats_struct_matches_header():
+    src = open(HEADER).read()
+    body = src[src.index("typedef struct mp_stats {"):src.index("} mp_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"(double|int64_t|int32_t)\s+(\w+);", body)
+    assert [f for _, f in fields] == [f for f, _ in mp.MpStats._fields_]
+    sizes = {"double": 8, "int64_t": 8, "int32_t": 4}
+    assert sum(sizes[t] for t, _ in fields) == ctypes.sizeof(mp.MpStats)
+
+
 def test_strerror_never_null(lib):
     for code in (0, -1, -2, -3, -4, 12345):
         assert isinstance(lib.mp_strerror(code), bytes)

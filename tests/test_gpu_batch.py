@@ -1,0 +1,181 @@
+"""GPU parity of mp_batch: many series of uneven length, mixed window length
+and distance, in one launch (the persistent band kernel over the job table,
+the simple kernel for short or generic-p jobs), its captured-graph replay and
+its autotuner. Every job is checked against the oracle run on that series
+alone."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.parity import check_profile
+
+pytestmark = pytest.mark.gpu
+
+KINDS = {"aamp": 0, "pnorm": 1, "acamp": 2}
+
+
+def _note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_1901_05708_amd as m
+    m.load()
+    return m
+
+
+def _jobs(mp, specs):
+    return [mp.Job(n=len(T), m=m, kind=KINDS[kind], excl=excl, R=R, p=p)
+            for T, m, kind, p, excl, R in specs]
+
+
+def _run(mp, specs, precision="fp64", out=None, T_cat=None):
+    import torch
+    if T_cat is None:
+        T_cat = torch.as_tensor(np.concatenate([sp[0] for sp in specs]), device="cuda")
+    P, I = mp.batch(T_cat, _jobs(mp, specs), precision=precision, out=out)
+    torch.cuda.synchronize()
+    return P, I, T_cat
+
+
+def _check(specs, P, I, rtol, label, rows_per_job=None):
+    P, I = P.cpu().numpy(), I.cpu().numpy()
+    off = 0
+    for b, (T, m, kind, p, excl, R) in enumerate(specs):
+        N = len(T) - m + 1
+        e = excl or W.excl_default(m)
+        atol = 1e-6 if kind == "acamp" else 0.0
+        if rows_per_job is None:
+            rows = None
+            Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=e)
+            Pg, Ig = P[off:off + N], I[off:off + N]
+        else:
+            rows = W.sample_rows(N, min(N, rows_per_job), seed=b)
+            Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=e, rows=rows)
+            Pg, Ig = P[off:off + N][rows], I[off:off + N][rows]
+        check_profile(T, m, kind, p, e, Pg, Ig, Pr, Ir, Qr, rtol, atol, rows=rows,
+                      label=f"{label} job {b} ({kind} p={p} n={len(T)} m={m})")
+        off += N
+
+
+def _mixed_specs(seed, count, nmax, kinds, with_runs=True):
+    rng = np.random.default_rng(seed)
+    specs = []
+    for b in range(count):
+        kind, p = kinds[b % len(kinds)]
+        m = int(rng.choice([4, 8, 16, 32, 64]))
+        n = int(rng.integers(m, nmax))
+        T = np.cumsum(rng.standard_normal(n)) if rng.random() < 0.6 else W.noisy_sine(n, rng)
+        if with_runs and kind == "acamp" and n > 400:
+            s = int(rng.integers(0, n - 150))
+            T[s:s + 120] = T[s]                       # a constant run
+        excl = int(rng.choice([0, 0, 1, 3]))
+        specs.append((T, m, kind, p, excl, 0))
+    return specs
+
+
+ALL = [("aamp", 2.0), ("acamp", 2.0), ("pnorm", 1.0), ("pnorm", 3.0), ("pnorm", 1.5)]
+BAND = [("aamp", 2.0), ("acamp", 2.0), ("pnorm", 1.0), ("pnorm", 3.0)]
+
+
+def test_batch_mixed_fp64(mp):
+    """Lengths from m (one window) to 4000, every distance incl. generic p
+    (simple kernel), short jobs below half a band, exclusion zones 1..ceil(m/4)."""
+    specs = _mixed_specs(1, 30, 4000, ALL)
+    specs.append((np.linspace(0, 1, 50), 50, "aamp", 2.0, 0, 0))       # n == m: no pairs
+    specs.append((np.cumsum(np.ones(40)), 8, "acamp", 2.0, 40, 0))     # N <= excl
+    _note(f"batch mixed fp64 jobs={len(specs)}")
+    P, I, _ = _run(mp, specs)
+    _check(specs, P, I, 1e-9, "mixed")
+
+
+def test_batch_fp32(mp):
+    specs = _mixed_specs(2, 16, 5000, BAND)
+    specs = [(T, m, k, p, e, R) for T, m, k, p, e, R in specs if len(T) > 1500]
+    _note(f"batch fp32 jobs={len(specs)}")
+    P, I, _ = _run(mp, specs, precision="fp32")
+    _check(specs, P, I, 1e-4, "fp32")
+
+
+def test_batch_single_kind_kernels(mp):
+    """Batches of one distance use that distance's own kernel."""
+    for kind, p in BAND:
+        specs = [(np.cumsum(np.random.default_rng(40 + k).standard_normal(1200 + 300 * k)), 24,
+                  kind, p, 0, 0) for k in range(4)]
+        _note(f"batch single kind {kind} p={p}")
+        P, I, _ = _run(mp, specs)
+        _check(specs, P, I, 1e-9, f"single-{kind}{p}")
+
+
+def test_batch_matches_single_series_calls(mp):
+    import torch
+    specs = _mixed_specs(3, 8, 3000, BAND, with_runs=False)
+    _note("batch vs single calls")
+    P, I, _ = _run(mp, specs)
+    P, I = P.cpu().numpy(), I.cpu().numpy()
+    off = 0
+    for T, m, kind, p, excl, R in specs:
+        N = len(T) - m + 1
+        Td = torch.as_tensor(T, device="cuda")
+        e = excl or None
+        if kind == "aamp":
+            Ps, Is = mp.aamp(Td, m, excl=e)
+        elif kind == "acamp":
+            Ps, Is = mp.acamp(Td, m, excl=e)
+        else:
+            Ps, Is = mp.pnorm(Td, m, p=p, excl=e)
+        torch.cuda.synchronize()
+        Ps, Is = Ps.cpu().numpy(), Is.cpu().numpy()
+        same = Is == I[off:off + N]
+        assert same.mean() > 0.99
+        assert np.allclose(P[off:off + N], Ps, rtol=1e-9, atol=1e-6 if kind == "acamp" else 0)
+        off += N
+
+
+def test_batch_graph_replay(mp):
+    """The second identical call replays the captured graph and reproduces the
+    first bit for bit; after new data is written into the same buffers, a
+    replay computes the new profiles."""
+    import torch
+    specs = _mixed_specs(5, 10, 3000, BAND)
+    _note("batch graph replay")
+    mp.set_profiling(False)                  # clears the counters
+    P1, I1, T_cat = _run(mp, specs)          # tunes, captures and launches
+    assert mp.profile_read()["graph_replays"] == 0
+    P1c, I1c = P1.cpu().numpy().copy(), I1.cpu().numpy().copy()
+    P1.fill_(-1.0)
+    I1.fill_(-7)
+    P2, I2, _ = _run(mp, specs, out=(P1, I1), T_cat=T_cat)
+    assert mp.profile_read()["graph_replays"] == 1
+    assert np.array_equal(P2.cpu().numpy(), P1c) and np.array_equal(I2.cpu().numpy(), I1c)
+    _check(specs, P2, I2, 1e-9, "replay")
+    # new data, same pointers
+    rng = np.random.default_rng(99)
+    specs2 = [(np.cumsum(rng.standard_normal(len(T))), m, k, p, e, R)
+              for T, m, k, p, e, R in specs]
+    T_cat.copy_(torch.as_tensor(np.concatenate([sp[0] for sp in specs2]), device="cuda"))
+    P4, I4, _ = _run(mp, specs, out=(P1, I1), T_cat=T_cat)
+    assert mp.profile_read()["graph_replays"] == 2
+    _check(specs2, P4, I4, 1e-9, "replay-new-data")
+
+
+def test_batch_workload_shape_sampled(mp):
+    """The batch workload's recipe (random walks and noisy sines, m in
+    {32, 64, 128, 256}, AAMP / ACAMP) at reduced count and length, every job
+    checked on sampled rows, in FP64 and FP32."""
+    import torch
+    jobs = W.batch(seed=4, count=48, nrange=(2048, 12000))
+    specs = [(jb.T, jb.m, jb.kind, 2.0, 0, 0) for jb in jobs]
+    for prec, rtol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        _note(f"batch workload shape {prec} jobs={len(specs)}")
+        P, I, _ = _run(mp, specs, precision=prec)
+        _check(specs, P, I, rtol, f"workload-{prec}", rows_per_job=24)
+    st = mp.profile_read()
+    assert st["ms_autotune"] >= 0.0
