@@ -1,19 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the matrix-profile hot path on one MI355X.
 
-Workload (one step = one full call of the hot path: window statistics and
-difference streams, the diagonal sweep, FP64 rescoring / finalisation):
-z-normalized profile (ACAMP) of a random walk of n = 131072 samples with 20
-constant runs and 10 planted motif pairs, m = 256, exclusion |i - j| < m/4.
-The series is resident in HBM before timing starts. Prints one JSON line.
+Headline workload (one step = one full call of the hot path: window
+statistics and difference streams, the diagonal sweep, FP64 rescoring,
+certification and exact search): z-normalized profile (ACAMP) of a random
+walk of n = 131072 samples with 20 constant runs and 10 planted motif pairs,
+m = 256, exclusion |i - j| < m/4. Timed in FP64 (``value``) and in
+FP32 + FP64 refresh (``fp32_refresh``), with the gain between them.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32]
+Batch workload (``batch``): 512 random-walk / noisy-sine series of length
+U{2048..65536}, m in {32, 64, 128, 256}, AAMP / ACAMP mixed, one mp_batch call
+per step (autotuned, captured once, then replayed as a HIP graph), in both
+precisions.
+
+Inputs are resident in HBM before timing starts. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-cpu]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +37,9 @@ METRIC = "subsequence-pair distances/s (G pairs/s) FP32+refresh vs FP64, at stat
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # algorithmic lane-operations per pair (O(1) update + row min + column min)
 OPS_PER_PAIR = {"aamp": 5, "acamp": 6, "pnorm1": 6, "pnorm3": 8}
+# HBM traffic of the sweep kernel, from rocprofv3 counters (see that file)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_band_acamp_rw128k_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1901_05708_amd", "csrc", "k_sweep_band.hip")
 
 
 def parse():
@@ -34,8 +47,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--refresh", type=int, default=0, help="refresh interval R (0: library default)")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 + refresh runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: auto)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -80,13 +94,133 @@ def cpu_baseline(T, m, excl, kind, P_gpu, I_gpu, rows_hint=0):
     }
 
 
+def sweep_traffic():
+    """HBM bytes per launch of the FP64 ACAMP sweep from the committed
+    rocprofv3 counter summary, or None when the kernel source changed since
+    the counters were taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    want = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    got = re.search(r"traffic_bytes_per_launch:\s*([0-9]+)", text)
+    if not want or not got:
+        return None
+    have = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    return int(got.group(1)) if have == want.group(1) else None
+
+
+def timed(fn, steps, warmup, stream):
+    """ms per call of fn over `steps` calls after `warmup` untimed ones,
+    bracketed by stream events and device synchronisation."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def headline(args, mp, W, torch):
+    T, m, planted = W.rw128k()
+    n = len(T)
+    excl = W.excl_default(m)
+    pairs = mp.pair_count(n, m, excl)
+    Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {"T": T, "m": m, "excl": excl, "pairs": pairs, "n": n}
+    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32",)):
+        out = {}
+
+        def step():
+            out["PI"] = mp.acamp(Td, m, excl=excl, precision=prec, stream=stream)
+
+        # timed region with the library's phase events on (no host syncs)
+        mp.set_profiling(True)
+        t0 = time.perf_counter()
+        ms = timed(step, args.steps, args.warmup, stream)
+        wall = time.perf_counter() - t0
+        prof = mp.profile_read()
+        mp.set_profiling(False)
+        calls = max(1, prof["calls"])
+        res[prec] = {
+            "ms_per_step": ms,
+            "value": pairs / (ms * 1e-3) / 1e9,
+            "sweep_ms": prof["ms_sweep"] / calls,
+            "prep_ms": prof["ms_prep"] / calls,
+            "finalize_ms": prof["ms_finalize"] / calls,
+            "fallback_rows": prof["fallback_rows"] / calls,
+            "refresh_rows": prof["refresh_rows"],
+            "diags_per_lane": prof["diags_per_lane"],
+            "items": prof["items"],
+            "wall_s": wall,
+            "P": out["PI"][0].cpu().numpy(),
+            "I": out["PI"][1].cpu().numpy(),
+        }
+    return res
+
+
+def batch_workload(args, mp, W, torch):
+    import numpy as np
+    jobs_np = W.batch()
+    jobs = [mp.Job(n=len(jb.T), m=jb.m, kind=mp.KIND_AAMP if jb.kind == "aamp" else mp.KIND_ACAMP)
+            for jb in jobs_np]
+    T_cat = torch.as_tensor(np.concatenate([jb.T for jb in jobs_np]), device="cuda")
+    table, total_n, total_out = mp.batch_layout(jobs)
+    pairs = sum(mp.pair_count(jb.n, jb.m, mp.default_excl(jb.m)) for jb in jobs)
+    stream = torch.cuda.current_stream()
+    res = {"jobs": len(jobs), "pairs": pairs, "samples": int(total_n)}
+    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32",)):
+        P = torch.empty(total_out, dtype=torch.float64, device="cuda")
+        I = torch.empty(total_out, dtype=torch.int64, device="cuda")
+        mp.set_profiling(False)       # clears autotune time and replay counters
+        t0 = time.perf_counter()
+        mp.batch(T_cat, jobs, precision=prec, out=(P, I), table=table, stream=stream)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        tune = mp.profile_read()["ms_autotune"]
+
+        def step():
+            mp.batch(T_cat, jobs, precision=prec, out=(P, I), table=table, stream=stream)
+
+        ms = timed(step, args.batch_steps, 1, stream)
+        replays = mp.profile_read()["graph_replays"]
+        # one profiled call (launched directly) for the phase split
+        mp.set_profiling(True)
+        step()
+        prof = mp.profile_read()
+        mp.set_profiling(False)
+        res[prec] = {
+            "ms_per_step": round(ms, 3),
+            "value": round(pairs / (ms * 1e-3) / 1e9, 3),
+            "graph_replays": replays,
+            "first_call_s": round(first, 3),
+            "autotune_ms": round(tune, 1),
+            "refresh_rows": prof["refresh_rows"],
+            "diags_per_lane": prof["diags_per_lane"],
+            "fallback_rows_per_step": prof["fallback_rows"],
+            "phases_ms": {"prep": round(prof["ms_prep"], 3), "sweep": round(prof["ms_sweep"], 3),
+                          "finalize": round(prof["ms_finalize"], 3)},
+        }
+    if "fp32" in res:
+        res["fp32_gain"] = round(res["fp32"]["value"] / res["fp64"]["value"], 4)
+    res["workload"] = ("512 series (seed 4): random walk or noisy sine, n ~ U{2048..65536}, "
+                       "m in {32,64,128,256}, AAMP/ACAMP 50/50, excl = ceil(m/4); one mp_batch "
+                       "call per step, graph replay")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); every GPU box here has "
               "one GPU and this build has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_1901_05708_amd as mp
     import workloads as W
@@ -95,81 +229,67 @@ def main():
         print("bench.py needs a HIP GPU", file=sys.stderr)
         sys.exit(1)
     mp.load()
-    T, m, planted = W.rw128k()
-    n = len(T)
-    excl = W.excl_default(m)
-    kind = "acamp"
-    pairs = mp.pair_count(n, m, excl)
-    Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    def step():
-        return mp.acamp(Td, m, excl=excl, precision=args.precision, R=args.refresh, stream=stream)
-
-    for _ in range(args.warmup):
-        P, I = step()
-    torch.cuda.synchronize()
-
-    mp.set_profiling(True)
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(args.steps):
-        P, I = step()
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = mp.profile_read()
-    mp.set_profiling(False)
-    ms_total = start.elapsed_time(end)
-    ms_step = ms_total / args.steps
-    value = pairs / (ms_step * 1e-3) / 1e9
-
-    sweep_ms = prof["ms_sweep"] / max(1, prof["calls"])
-    ops = OPS_PER_PAIR[kind] * pairs
-    achieved = ops / (sweep_ms * 1e-3) / 1e12
+    h = headline(args, mp, W, torch)
+    f64 = h["fp64"]
+    pairs = h["pairs"]
+    ops = OPS_PER_PAIR["acamp"] * pairs
+    achieved = ops / (f64["sweep_ms"] * 1e-3) / 1e12
     peak = PEAK_LANE_OPS / 1e12
-
-    fallback = prof["fallback_rows"] / max(1, prof["calls"])
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(f64["value"], 3),
         "unit": "Gpairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(f64["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": "acamp_rw128k: z-normalized matrix profile, random walk n=131072 with 20 "
                         "constant runs and 10 planted motif pairs, m=256, excl=64",
-            "n": n, "m": m, "excl": excl, "pairs": pairs, "precision": args.precision,
-            "refresh_rows": prof["refresh_rows"], "diags_per_lane": prof["diags_per_lane"],
-            "items": prof["items"], "fallback_rows_per_step": fallback,
+            "n": h["n"], "m": h["m"], "excl": h["excl"], "pairs": pairs, "precision": "fp64",
+            "refresh_rows": f64["refresh_rows"], "diags_per_lane": f64["diags_per_lane"],
+            "items": f64["items"], "fallback_rows_per_step": f64["fallback_rows"],
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_sweep_band",
+            "kernel": "k_sweep_band (ACAMP, FP64)",
             "achieved": round(achieved, 3),
             "peak": round(peak, 3),
             "unit": "Tlane-ops/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
-            "ops_per_pair": OPS_PER_PAIR[kind],
-            "kernel_ms": round(sweep_ms, 4),
+            "traffic": sweep_traffic(),
+            "ops_per_pair": OPS_PER_PAIR["acamp"],
+            "kernel_ms": round(f64["sweep_ms"], 4),
         },
         "phases_ms_per_step": {
-            "prep": round(prof["ms_prep"] / max(1, prof["calls"]), 4),
-            "sweep": round(sweep_ms, 4),
-            "finalize": round(prof["ms_finalize"] / max(1, prof["calls"]), 4),
+            "prep": round(f64["prep_ms"], 4),
+            "sweep": round(f64["sweep_ms"], 4),
+            "finalize": round(f64["finalize_ms"], 4),
         },
-        "wall_s": round(wall, 3),
+        "wall_s": round(f64["wall_s"], 3),
     }
+    if "fp32" in h:
+        f32 = h["fp32"]
+        out["fp32_refresh"] = {
+            "value": round(f32["value"], 3),
+            "ms_per_step": round(f32["ms_per_step"], 4),
+            "gain_vs_fp64": round(f32["value"] / f64["value"], 4),
+            "rtol": 1e-4,
+            "refresh_rows": f32["refresh_rows"],
+            "diags_per_lane": f32["diags_per_lane"],
+            "fallback_rows_per_step": f32["fallback_rows"],
+            "phases_ms_per_step": {"prep": round(f32["prep_ms"], 4),
+                                   "sweep": round(f32["sweep_ms"], 4),
+                                   "finalize": round(f32["finalize_ms"], 4)},
+            "sweep_gain_vs_fp64": round(f64["sweep_ms"] / f32["sweep_ms"], 4),
+        }
+    if not args.no_batch:
+        out["batch"] = batch_workload(args, mp, W, torch)
     if args.copy_calib > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
         # calibrate the ones read for the sweep
@@ -180,7 +300,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = int(src.numel() * 8)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(T, m, excl, kind, P.cpu().numpy(), I.cpu().numpy(),
+        out["cpu_baseline"] = cpu_baseline(h["T"], h["m"], h["excl"], "acamp", f64["P"], f64["I"],
                                            args.cpu_rows)
     print(json.dumps(out), flush=True)
 
