@@ -32,7 +32,12 @@
  *    statistics and FP64 rescoring of every winner; rows it cannot certify
  *    within MP_FP32_RTOL are recomputed in FP64.
  *  - R is the refresh interval (rows between exact FP64 restarts of the
- *    recurrence); R = 0 lets the library choose.
+ *    recurrence). R = 0 lets the library choose: the first call with a given
+ *    series shape (n, m, distance, excl, precision) times a few candidate
+ *    refresh intervals and band widths on the call's own input, on a library
+ *    stream ordered after the caller's stream, and caches the fastest (this
+ *    first call blocks the host until the trials end; mp_stats.ms_autotune
+ *    reports their time). Set R > 0 to skip the trials.
  *  - Errors: functions return MP_OK (0) or a negative code. Arguments are
  *    validated before any HIP call; on error nothing is enqueued and P, I are
  *    left untouched (except MP_EHIP, after which their content is undefined).

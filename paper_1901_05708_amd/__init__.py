@@ -106,13 +106,23 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-def _series(T, m: int):
+def _check_values(T):
+    """The ABI's precondition on the samples: finite, |t| < 1e30 (this reads
+    the tensor back, so it synchronises with the device)."""
+    import torch
+    if T.numel() and not bool(torch.all(torch.isfinite(T) & (T.abs() < 1e30))):
+        raise ValueError("T must be finite with |t| < 1e30")
+
+
+def _series(T, m: int, validate: bool = True):
     import torch
     if not isinstance(T, torch.Tensor) or T.device.type != "cuda":
         raise TypeError("T must be a torch tensor on a HIP (cuda) device")
     if T.dtype != torch.float64 or T.dim() != 1:
         raise TypeError("T must be a 1-D float64 tensor")
     T = T.contiguous()
+    if validate:
+        _check_values(T)
     n = T.shape[0]
     if not (1 <= m <= n):
         raise ValueError("need 1 <= m <= len(T)")
@@ -122,26 +132,30 @@ def _series(T, m: int):
     return T, n, N, P, I
 
 
-def aamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, stream=None):
-    """Pure Euclidean matrix profile (mp_aamp). Returns (P, I) tensors."""
-    T, n, N, P, I = _series(T, m)
+def aamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, stream=None,
+         validate: bool = True):
+    """Pure Euclidean matrix profile (mp_aamp). Returns (P, I) tensors.
+    validate=True first checks the ABI's precondition on T (finite, |t| <
+    1e30), which synchronises with the device; pass False in timed loops."""
+    T, n, N, P, I = _series(T, m, validate)
     _check(load().mp_aamp(T.data_ptr(), n, m, excl or 0, _prec(precision), R,
                           P.data_ptr(), I.data_ptr(), _stream(stream)))
     return P, I
 
 
 def pnorm(T, m: int, p: float, excl: Optional[int] = None, precision="fp64", R: int = 0,
-          stream=None):
+          stream=None, validate: bool = True):
     """p-norm matrix profile (mp_pnorm), real p >= 1. Returns (P, I)."""
-    T, n, N, P, I = _series(T, m)
+    T, n, N, P, I = _series(T, m, validate)
     _check(load().mp_pnorm(T.data_ptr(), n, m, float(p), excl or 0, _prec(precision), R,
                            P.data_ptr(), I.data_ptr(), _stream(stream)))
     return P, I
 
 
-def acamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, stream=None):
+def acamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, stream=None,
+         validate: bool = True):
     """z-normalized matrix profile (mp_acamp). Returns (P, I)."""
-    T, n, N, P, I = _series(T, m)
+    T, n, N, P, I = _series(T, m, validate)
     _check(load().mp_acamp(T.data_ptr(), n, m, excl or 0, _prec(precision), R,
                            P.data_ptr(), I.data_ptr(), _stream(stream)))
     return P, I
@@ -168,7 +182,8 @@ def batch_layout(jobs: Sequence[Job]):
     return table, t_off, out_off
 
 
-def batch(T_cat, jobs: Sequence[Job], precision="fp64", stream=None, out=None, table=None):
+def batch(T_cat, jobs: Sequence[Job], precision="fp64", stream=None, out=None, table=None,
+          validate: bool = True):
     """Matrix profiles of many series in one call (mp_batch). T_cat is the
     concatenation of the series; returns (P_cat, I_cat) with each job's
     outputs at its out_off (see batch_layout). Passing the same `out` tensors
@@ -183,6 +198,8 @@ def batch(T_cat, jobs: Sequence[Job], precision="fp64", stream=None, out=None, t
     if T_cat.dtype != torch.float64 or T_cat.device.type != "cuda" or T_cat.shape[0] < total_n:
         raise TypeError("T_cat must be a float64 cuda tensor holding every series")
     T_cat = T_cat.contiguous()
+    if validate:
+        _check_values(T_cat[:total_n])
     if out is None:
         P = torch.empty(max(total_out, 1), dtype=torch.float64, device=T_cat.device)
         I = torch.empty(max(total_out, 1), dtype=torch.int64, device=T_cat.device)

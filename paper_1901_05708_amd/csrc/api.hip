@@ -389,10 +389,11 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
     const bool want32 = precision == MP_FP32_REFRESH;
     const char *sw = std::getenv("MP_SWEEP");
     const std::string choice = sw ? sw : "auto";
+    // diagonals per lane of the FP32 sweep; the FP64 sweep always uses 8
+    // (16 FP64 diagonals per lane exceed the register file)
     int32_t kd = tu.kd;
     if (env_int("MP_KD", 0) == 16) kd = 16;
-    if (!want32) kd = 8;   // 16 FP64 diagonals per lane exceed the register file
-    const int64_t W = 64 * kd;
+    if (!want32) kd = 8;
     int force_fb = env_int("MP_FORCE_FALLBACK", 0);
     if (force_fb != 1 && force_fb != 2) force_fb = 0;
 
@@ -416,10 +417,13 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         j.I = sp.I;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         const int64_t ndiag = s.N - s.excl;
+        // the sweep this job would join decides its band width
+        const bool single = want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
+        const int64_t W = 64 * (single ? kd : 8);
         bool band = (sel & SEL_BAND) && ndiag >= W / 2 && choice != "simple";
         if (choice == "band" && (sel & SEL_BAND) && ndiag > 0) band = true;
         if (ndiag <= 0) band = false;
-        s.fp32 = (want32 && band && s.m >= FP32_MIN_M) ? 1 : 0;
+        s.fp32 = (single && band) ? 1 : 0;
         int64_t rows = 0, nb = 0;
         if (band) {
             rows = band_rows_total(s.N, s.excl, W, &nb);
@@ -596,48 +600,6 @@ int finish_profile(EvSet &es, const Batch &b, const Layout &L, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// single series: a batch of one job, tables written on the stream
-// ---------------------------------------------------------------------------
-int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
-               int32_t precision, int32_t R, double *P, int64_t *I, void *stream)
-{
-    Spec sp;
-    RC_TRY(make_spec(T, n, m, kind, p, excl, R, P, I, &sp));
-    RC_TRY(check_precision(precision));
-    std::lock_guard<std::recursive_mutex> lk(g_mu);
-    Workspace *w = nullptr;
-    int dev = 0;
-    RC_TRY(get_ws(&w, &dev));
-    hipStream_t st = (hipStream_t)stream;
-
-    Layout L;
-    RC_TRY(make_layout({sp}, precision, Tuning(), *w, &L));
-    RC_TRY(ensure_arrays(*w, L.stream_total, L.key_total));
-    RC_TRY(ensure_band1(*w, L.band_entries));
-    bind(L, *w);
-    Tables t;
-    t.jobs = w->job1;
-    t.row_base = w->row_base1;
-    t.band = w->band1;
-    t.flags = w->flag1;
-    t.pivots = w->pivots1;
-    const Batch b = make_batch(L, *w, t);
-
-    EvSet es;
-    bool prof = false;
-    RC_TRY(prof_begin(st, &es, &prof));
-    RowBase4 rb;
-    std::memset(&rb, 0, sizeof(rb));
-    rb.count = (int32_t)L.row_base.size();
-    for (int32_t k = 0; k < rb.count && k < 4; ++k) rb.v[k] = L.row_base[k];
-    HIP_TRY(launch_store_job(L.jobs[0], rb, w->job1, w->row_base1, st), "job table");
-    RC_TRY(enqueue(b, L, st, prof ? &es : nullptr));
-    if (prof) RC_TRY(finish_profile(es, b, L, st));
-    g_last_code = MP_OK;
-    return MP_OK;
-}
-
-// ---------------------------------------------------------------------------
 // batches: autotuner, uploaded tables and captured graphs
 // ---------------------------------------------------------------------------
 struct TuneEntry {
@@ -792,6 +754,83 @@ int autotune(const std::vector<Spec> &specs, int32_t precision, Workspace &w, hi
     return rc;
 }
 
+// Tuning of a launch shape: cached per device, precision and shape (the job
+// table without offsets); computed by autotune() on first use unless
+// MP_AUTOTUNE=0, in which case the defaults apply.
+int tuning_for(const std::vector<Spec> &specs, const mp_job *jobs, int32_t njobs,
+               int32_t precision, Workspace &w, int dev, hipStream_t st, Tuning *tu)
+{
+    const std::vector<int64_t> shape = shape_of(jobs, njobs);
+    for (const TuneEntry &te : g_tune)
+        if (te.dev == dev && te.precision == precision && te.shape == shape) {
+            *tu = te.best;
+            return MP_OK;
+        }
+    *tu = Tuning();
+    if (env_int("MP_AUTOTUNE", 1) == 0) return MP_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    RC_TRY(autotune(specs, precision, w, st, tu));
+    const auto t1 = std::chrono::steady_clock::now();
+    g_prof.acc.ms_autotune += std::chrono::duration<double, std::milli>(t1 - t0).count();
+    g_tune.push_back(TuneEntry{dev, precision, shape, *tu});
+    return MP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single series: a batch of one job, tables written on the stream
+// ---------------------------------------------------------------------------
+int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
+               int32_t precision, int32_t R, double *P, int64_t *I, void *stream)
+{
+    Spec sp;
+    RC_TRY(make_spec(T, n, m, kind, p, excl, R, P, I, &sp));
+    RC_TRY(check_precision(precision));
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    Workspace *w = nullptr;
+    int dev = 0;
+    RC_TRY(get_ws(&w, &dev));
+    hipStream_t st = (hipStream_t)stream;
+
+    // R = 0: the refresh interval (and, in FP32, the band width) is tuned per
+    // series shape on first use
+    Tuning tu;
+    if (sp.R == 0) {
+        mp_job shape_job;
+        std::memset(&shape_job, 0, sizeof(shape_job));
+        shape_job.n = sp.n;
+        shape_job.m = sp.m;
+        shape_job.kind = sp.kind;
+        shape_job.excl = sp.excl;
+        shape_job.p = sp.p;
+        RC_TRY(tuning_for({sp}, &shape_job, 1, precision, *w, dev, st, &tu));
+    }
+    Layout L;
+    RC_TRY(make_layout({sp}, precision, tu, *w, &L));
+    RC_TRY(ensure_arrays(*w, L.stream_total, L.key_total));
+    RC_TRY(ensure_band1(*w, L.band_entries));
+    bind(L, *w);
+    Tables t;
+    t.jobs = w->job1;
+    t.row_base = w->row_base1;
+    t.band = w->band1;
+    t.flags = w->flag1;
+    t.pivots = w->pivots1;
+    const Batch b = make_batch(L, *w, t);
+
+    EvSet es;
+    bool prof = false;
+    RC_TRY(prof_begin(st, &es, &prof));
+    RowBase4 rb;
+    std::memset(&rb, 0, sizeof(rb));
+    rb.count = (int32_t)L.row_base.size();
+    for (int32_t k = 0; k < rb.count && k < 4; ++k) rb.v[k] = L.row_base[k];
+    HIP_TRY(launch_store_job(L.jobs[0], rb, w->job1, w->row_base1, st), "job table");
+    RC_TRY(enqueue(b, L, st, prof ? &es : nullptr));
+    if (prof) RC_TRY(finish_profile(es, b, L, st));
+    g_last_code = MP_OK;
+    return MP_OK;
+}
+
 int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
               double *P_cat, int64_t *I_cat, void *stream)
 {
@@ -837,23 +876,8 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
         it = g_graphs.end();
     }
     if (it == g_graphs.end()) {
-        // tuning of this batch shape
         Tuning tu;
-        const std::vector<int64_t> shape = shape_of(jobs, njobs);
-        bool tuned = false;
-        for (const TuneEntry &te : g_tune)
-            if (te.dev == dev && te.precision == precision && te.shape == shape) {
-                tu = te.best;
-                tuned = true;
-                break;
-            }
-        if (!tuned && env_int("MP_AUTOTUNE", 1) != 0) {
-            const auto t0 = std::chrono::steady_clock::now();
-            RC_TRY(autotune(specs, precision, *w, st, &tu));
-            const auto t1 = std::chrono::steady_clock::now();
-            g_prof.acc.ms_autotune += std::chrono::duration<double, std::milli>(t1 - t0).count();
-            g_tune.push_back(TuneEntry{dev, precision, shape, tu});
-        }
+        RC_TRY(tuning_for(specs, jobs, njobs, precision, *w, dev, st, &tu));
         GraphEntry e;
         e.dev = dev;
         e.precision = precision;

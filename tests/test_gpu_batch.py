@@ -179,3 +179,89 @@ def test_batch_workload_shape_sampled(mp):
         _check(specs, P, I, rtol, f"workload-{prec}", rows_per_job=24)
     st = mp.profile_read()
     assert st["ms_autotune"] >= 0.0
+
+
+def test_batch_replays_between_eager_calls(mp):
+    """Graph replays interleaved with the program's own eager work (single-
+    series calls that share the workspace, device syncs): every replay must
+    equal the eager result. A single call on a longer series grows the
+    workspace, which invalidates the captured graph; the next batch call must
+    rebuild it and still be right."""
+    import torch
+    specs = _mixed_specs(7, 6, 2500, BAND)
+    _note("batch replays between eager calls")
+    P0, I0, T_cat = _run(mp, specs)
+    ref_P, ref_I = P0.cpu().numpy().copy(), I0.cpu().numpy().copy()
+    _check(specs, P0, I0, 1e-9, "eager-replay-ref")
+    rng = np.random.default_rng(3)
+    for k in range(3):
+        # eager work of the program between the replays
+        Tx = torch.as_tensor(np.cumsum(rng.standard_normal(3000)), device="cuda")
+        Px, Ix = mp.acamp(Tx, 32)
+        torch.cuda.synchronize()
+        P, I, _ = _run(mp, specs, out=(P0, I0), T_cat=T_cat)
+        assert np.array_equal(P.cpu().numpy(), ref_P), f"replay {k}"
+        assert np.array_equal(I.cpu().numpy(), ref_I), f"replay {k}"
+    # grow the workspace with a long single series, then replay again
+    big = np.cumsum(rng.standard_normal(int(T_cat.numel()) + 50000))
+    Pb, Ib = mp.aamp(torch.as_tensor(big, device="cuda"), 64)
+    torch.cuda.synchronize()
+    P, I, _ = _run(mp, specs, out=(P0, I0), T_cat=T_cat)
+    assert np.array_equal(P.cpu().numpy(), ref_P) and np.array_equal(I.cpu().numpy(), ref_I)
+
+
+@pytest.mark.slow
+def test_batch_full_workload_sampled(mp):
+    """The full 512-series batch workload (3.9e11 pairs) in one call, FP64 and
+    FP32 + refresh; the oracle checks 24 random series on 32 sampled rows each
+    and every series on its first row."""
+    jobs = W.batch()
+    specs = [(jb.T, jb.m, jb.kind, 2.0, 0, 0) for jb in jobs]
+    rng = np.random.default_rng(12)
+    pick = set(rng.choice(len(specs), size=24, replace=False).tolist())
+    for prec, rtol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        _note(f"batch full workload {prec} jobs={len(specs)}")
+        P, I, _ = _run(mp, specs, precision=prec)
+        P, I = P.cpu().numpy(), I.cpu().numpy()
+        off = 0
+        for b, (T, m, kind, p, excl, R) in enumerate(specs):
+            N = len(T) - m + 1
+            e = W.excl_default(m)
+            rows = W.sample_rows(N, 32, seed=b) if b in pick else np.array([0])
+            Pr, Ir, Qr = oracle.profile(T, m, kind, excl=e, rows=rows)
+            check_profile(T, m, kind, 2.0, e, P[off:off + N][rows], I[off:off + N][rows], Pr, Ir,
+                          Qr, rtol, 1e-6 if kind == "acamp" else 0.0, rows=rows, sample=8,
+                          label=f"full-{prec} job {b}")
+            off += N
+
+
+def test_fp32_wide_bands_with_short_windows(mp, monkeypatch):
+    """Regression: with 16 diagonals per lane chosen for the FP32 sweep, jobs
+    whose windows are too short for FP32 (m < 32) run the FP64 sweep, whose
+    bands stay 512 wide; their band tables must use that width. Checked for a
+    batch and for single-series calls."""
+    import torch
+    monkeypatch.setenv("MP_KD", "16")
+    rng = np.random.default_rng(21)
+    specs = []
+    for k, m in enumerate([8, 16, 24, 48, 64, 24]):
+        T = np.cumsum(rng.standard_normal(1500 + 400 * k))
+        specs.append((T, m, "acamp" if k % 2 else "aamp", 2.0, 0, 0))
+    _note("fp32 wide bands, short windows (batch)")
+    P, I, _ = _run(mp, specs, precision="fp32")
+    P, I = P.cpu().numpy(), I.cpu().numpy()
+    off = 0
+    for b, (T, m, kind, p, excl, R) in enumerate(specs):
+        N, e = len(T) - m + 1, W.excl_default(m)
+        Pr, Ir, Qr = oracle.profile(T, m, kind, excl=e)
+        rtol = 1e-9 if m < 32 else 1e-4
+        check_profile(T, m, kind, p, e, P[off:off + N], I[off:off + N], Pr, Ir, Qr, rtol,
+                      1e-6 if kind == "acamp" else 0.0, label=f"wide-{b}")
+        off += N
+    _note("fp32 wide bands, short windows (single)")
+    T, m = specs[2][0], 24
+    Ps, Is = mp.acamp(torch.as_tensor(T, device="cuda"), m, precision="fp32")
+    torch.cuda.synchronize()
+    Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=W.excl_default(m))
+    check_profile(T, m, "acamp", 2.0, W.excl_default(m), Ps.cpu().numpy(), Is.cpu().numpy(),
+                  Pr, Ir, Qr, 1e-9, 1e-6, label="wide-single")
