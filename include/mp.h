@@ -173,6 +173,9 @@ typedef struct mp_stats {
                                 whether or not profiling is on)                  */
     int64_t pairs;           /* admissible unordered pairs                      */
     int64_t fallback_rows;   /* rows recomputed exactly in FP64                 */
+    int64_t pairs_visited;   /* pairs the sweeps visited, counted only in the
+                                test mode MP_COUNT_PAIRS=1 (else 0); equals
+                                pairs when the work split is exact               */
     int32_t calls;           /* calls accumulated                               */
     int32_t sweep_launches;  /* sweep kernel launches accumulated               */
     int32_t refresh_rows;    /* R of the most recent call (its first band-swept job) */

@@ -47,6 +47,7 @@ class MpStats(ctypes.Structure):
     _fields_ = [("ms_prep", ctypes.c_double), ("ms_sweep", ctypes.c_double),
                 ("ms_finalize", ctypes.c_double), ("ms_autotune", ctypes.c_double),
                 ("pairs", ctypes.c_int64), ("fallback_rows", ctypes.c_int64),
+                ("pairs_visited", ctypes.c_int64),
                 ("calls", ctypes.c_int32), ("sweep_launches", ctypes.c_int32),
                 ("refresh_rows", ctypes.c_int32), ("diags_per_lane", ctypes.c_int32),
                 ("items", ctypes.c_int32), ("graph_replays", ctypes.c_int32)]

@@ -74,6 +74,7 @@ struct Workspace {
     double *fb_ub = nullptr;
     float *fb_pd = nullptr;            // FB_PIVOTS x key_cap
     int32_t *counters = nullptr;
+    unsigned long long *visits = nullptr;   // pair-visit counter of the test mode
     // tables of single-series calls (one job)
     Job *job1 = nullptr;
     int64_t *row_base1 = nullptr;
@@ -108,8 +109,9 @@ void free_arrays(Workspace &w)
 void free_ws(Workspace &w)
 {
     free_arrays(w);
-    void *ptrs[] = {w.job1, w.row_base1, w.flag1, w.pivots1, w.band1};
+    void *ptrs[] = {w.job1, w.row_base1, w.flag1, w.pivots1, w.band1, w.visits};
     for (void *p : ptrs) hipFree(p);
+    w.visits = nullptr;
     w.job1 = nullptr;
     w.row_base1 = w.band1 = nullptr;
     w.flag1 = w.pivots1 = nullptr;
@@ -153,6 +155,7 @@ int get_ws(Workspace **out, int *dev_out)
         RC_TRY(grow(&w.row_base1, 4, "workspace job table"));
         RC_TRY(grow(&w.flag1, 1, "workspace job table"));
         RC_TRY(grow(&w.pivots1, FB_PIVOTS, "workspace job table"));
+        RC_TRY(grow(&w.visits, 1, "workspace counter"));
     }
     *out = &w;
     *dev_out = dev;
@@ -214,6 +217,7 @@ int ensure_lib_stream(Workspace &w)
 struct EvSet {
     hipEvent_t ev[4];
     int32_t *fb_host = nullptr;   // pinned copy of the call's fallback count
+    unsigned long long *visits_host = nullptr;   // and of its pair-visit count
 };
 
 struct Prof {
@@ -230,7 +234,11 @@ int prof_begin(hipStream_t st, EvSet *es, bool *active)
     for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&es->ev[k]), "hipEventCreate");
     HIP_TRY(hipHostMalloc((void **)&es->fb_host, sizeof(int32_t), hipHostMallocDefault),
             "hipHostMalloc");
+    HIP_TRY(hipHostMalloc((void **)&es->visits_host, sizeof(unsigned long long),
+                          hipHostMallocDefault),
+            "hipHostMalloc");
     *es->fb_host = 0;
+    *es->visits_host = 0;
     HIP_TRY(hipEventRecord(es->ev[0], st), "hipEventRecord");
     return MP_OK;
 }
@@ -368,6 +376,7 @@ struct Layout {
     int32_t kd = 8;
     int64_t pairs = 0, items = 0;
     int32_t R_report = 0;
+    bool count = false;                  // pair-visit counting (test mode)
 };
 
 int env_int(const char *name, int dflt)
@@ -381,7 +390,8 @@ int env_int(const char *name, int dflt)
 // kernel (FP64 only: a single-precision request on such a job is served
 // exactly in FP64). Test hooks: MP_SWEEP=band|simple forces a kernel,
 // MP_KD=16 requests 16 diagonals per lane (FP32 only), MP_FORCE_FALLBACK=1|2
-// sends every row through the exact search.
+// sends every row through the exact search, MP_COUNT_PAIRS=1 makes the sweeps
+// count the pairs they visit (reported with profiling on).
 int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning &tu,
                 const Workspace &w, Layout *out)
 {
@@ -396,6 +406,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
     if (!want32) kd = 8;
     int force_fb = env_int("MP_FORCE_FALLBACK", 0);
     if (force_fb != 1 && force_fb != 2) force_fb = 0;
+    L.count = env_int("MP_COUNT_PAIRS", 0) == 1;
 
     std::vector<Job> cls[3];          // FP64 band, FP32 band, other
     std::vector<int64_t> rows_of[3];
@@ -543,6 +554,7 @@ Batch make_batch(const Layout &L, const Workspace &w, const Tables &t)
     fb.pd = w.fb_pd;
     fb.pd_stride = w.key_cap;
     fb.capacity = (int32_t)std::min<int64_t>(L.key_total, INT32_MAX);
+    b.visits = L.count ? w.visits : nullptr;
     return b;
 }
 
@@ -587,6 +599,10 @@ int finish_profile(EvSet &es, const Batch &b, const Layout &L, hipStream_t st)
 {
     HIP_TRY(hipMemcpyAsync(es.fb_host, b.fb.count, sizeof(int32_t), hipMemcpyDeviceToHost, st),
             "hipMemcpyAsync");
+    if (b.visits)
+        HIP_TRY(hipMemcpyAsync(es.visits_host, b.visits, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st),
+                "hipMemcpyAsync");
     HIP_TRY(hipEventRecord(es.ev[3], st), "hipEventRecord");
     g_prof.pending.push_back(es);
     mp_stats &a = g_prof.acc;
@@ -862,7 +878,8 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
     RC_TRY(get_ws(&w, &dev));
     hipStream_t st = (hipStream_t)stream;
     RC_TRY(ensure_lib_stream(*w));
-    const bool use_graph = !g_prof.on && env_int("MP_GRAPH", 1) != 0;
+    const bool use_graph =
+        !g_prof.on && env_int("MP_GRAPH", 1) != 0 && env_int("MP_COUNT_PAIRS", 0) != 1;
 
     // cached entry for this exact call?
     auto it = g_graphs.begin();
@@ -1013,6 +1030,7 @@ void mp_set_profiling(int on)
     for (auto &es : g_prof.pending) {
         for (int k = 0; k < 4; ++k) (void)hipEventDestroy(es.ev[k]);
         (void)hipHostFree(es.fb_host);
+        (void)hipHostFree(es.visits_host);
     }
     g_prof.pending.clear();
     g_prof.acc = mp_stats{};
@@ -1033,8 +1051,10 @@ int mp_profile_read(mp_stats *out)
         g_prof.acc.ms_sweep += b;
         g_prof.acc.ms_finalize += c;
         g_prof.acc.fallback_rows += *es.fb_host;
+        g_prof.acc.pairs_visited += (int64_t)*es.visits_host;
         for (int k = 0; k < 4; ++k) (void)hipEventDestroy(es.ev[k]);
         (void)hipHostFree(es.fb_host);
+        (void)hipHostFree(es.visits_host);
     }
     g_prof.pending.clear();
     *out = g_prof.acc;

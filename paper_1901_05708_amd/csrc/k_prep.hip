@@ -54,7 +54,8 @@ __global__ void k_window_stats(Batch b)
 //        dg_j = (t_{j+m-1} - mu_j) + (t_{j-1} - mu_{j-1}).
 //        Stored with z_j = -invn_j so that -rho = cov invn_i z_j.
 // Entries j >= N hold sentinels that make every pair touching them lose.
-// Also resets the launch's exact-search queue and the job's queue flag.
+// Also resets the launch's exact-search queue, the job's queue flag and the
+// pair-visit counter of the test mode.
 __global__ void k_streams(Batch b)
 {
     const Series s = load_uniform(&b.jobs[blockIdx.y]).s;
@@ -64,7 +65,10 @@ __global__ void k_streams(Batch b)
     if (j < s.N) s.keys[j] = KEY_NONE;
     if (j == 0) {
         b.fb.job_flag[blockIdx.y] = 0;
-        if (blockIdx.y == 0) *b.fb.count = 0;
+        if (blockIdx.y == 0) {
+            *b.fb.count = 0;
+            if (b.visits) *b.visits = 0;
+        }
     }
     const int m = s.m;
     double x = 0.0, y = 0.0, z = 0.0;

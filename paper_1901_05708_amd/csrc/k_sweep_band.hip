@@ -221,9 +221,10 @@ struct Streams<float> {
 
 // One work item: the diagonals [k_lo, k_lo + 64 KD) of series s, rows
 // [i0, i1). ring (NF x RING entries) and rowbuf (NRB x 64) are the wave's LDS.
-template <int KIND, int PC, int KD, typename F>
+template <int KIND, int PC, int KD, typename F, bool COUNT>
 __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, const int64_t i0,
-                                          const int64_t i1, F *ring, F *rowbuf)
+                                          const int64_t i1, F *ring, F *rowbuf,
+                                          unsigned long long *visits)
 {
     typedef Prec<F> P;
     constexpr int WD = 64 * KD;          // diagonals per item
@@ -399,6 +400,17 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
             reduce_step(-1, 0, v);
         }
         flush_cols(0, 1);   // column 0 has only the first row's pair
+        // Pair-visit count (test mode): the real pairs (j < N) of every step
+        // whose row belongs to this item. The last block may run up to KD - 1
+        // steps past i1; those rows belong to the next item and are not counted.
+        unsigned long long visited = 0;
+        auto count_row = [&](int64_t row) {
+            if (COUNT && row < i1) {
+                const int64_t left = N - (row + k_lo + (int64_t)KD * lane);
+                visited += (unsigned long long)max((int64_t)0, min((int64_t)KD, left));
+            }
+        };
+        count_row(i0);
 
         // ---- recurrence, KD steps per unrolled block --------------------------
         // Block tb needs local columns [tb + RING, tb + RING + KD) in the ring;
@@ -477,6 +489,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                     }
                 }
                 reduce_step(tau, q + 1, v);
+                count_row(i0 + 1 + tau);
                 if (q == KD - 1) {
                     // next block's row operands (rows past i1 read padding entries)
 #pragma unroll
@@ -509,6 +522,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 atomicMin(&s.keys[j], pack_key((double)v, (unsigned long long)i, gmask));
             }
         }
+        if (COUNT && visited) atomicAdd(visits, visited);
         lds_order();
     }
 }
@@ -516,7 +530,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
 // The persistent sweep over every band of every job of a launch. SELS is the
 // set of distance specialisations the launch holds: a single one gets a kernel
 // of its own; a mix dispatches per item (the branch is wave-uniform).
-template <uint32_t SELS, int KD, typename F>
+template <uint32_t SELS, int KD, typename F, bool COUNT>
 __global__ void __launch_bounds__(64) k_sweep_band(Batch b)
 {
     constexpr int RING = 64 * KD;
@@ -567,13 +581,13 @@ __global__ void __launch_bounds__(64) k_sweep_band(Batch b)
         pos += seg;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
-            band_item<AAMP, P_TWO, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
         else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
-            band_item<ACAMP, P_TWO, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+            band_item<ACAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
         else if ((SELS & SEL_P1) && sel == SEL_P1)
-            band_item<PNORM, P_ONE, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
-            band_item<PNORM, P_THREE, KD, F>(s, k_lo, i0, i0 + seg, ring, rowbuf);
+            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
     }
 }
 
@@ -622,23 +636,26 @@ hipError_t launch_plan(const Batch &b, hipStream_t st)
 namespace {
 
 // Kernel of a selector set: one of its own for a single specialisation,
-// otherwise the mixed kernel holding all band specialisations.
+// otherwise the mixed kernel holding all band specialisations. The
+// pair-counting test mode always uses the mixed kernel.
 template <int KD, typename F>
-const void *band_kernel(uint32_t sels)
+const void *band_kernel(uint32_t sels, bool count)
 {
+    if (count) return (const void *)k_sweep_band<SEL_BAND, KD, F, true>;
     switch (sels & SEL_BAND) {
-    case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP, KD, F>;
-    case SEL_ACAMP: return (const void *)k_sweep_band<SEL_ACAMP, KD, F>;
-    case SEL_P1: return (const void *)k_sweep_band<SEL_P1, KD, F>;
-    case SEL_P3: return (const void *)k_sweep_band<SEL_P3, KD, F>;
-    default: return (const void *)k_sweep_band<SEL_BAND, KD, F>;
+    case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP, KD, F, false>;
+    case SEL_ACAMP: return (const void *)k_sweep_band<SEL_ACAMP, KD, F, false>;
+    case SEL_P1: return (const void *)k_sweep_band<SEL_P1, KD, F, false>;
+    case SEL_P3: return (const void *)k_sweep_band<SEL_P3, KD, F, false>;
+    default: return (const void *)k_sweep_band<SEL_BAND, KD, F, false>;
     }
 }
 
-const void *band_kernel_for(uint32_t sels, int32_t kd, bool fp32)
+const void *band_kernel_for(uint32_t sels, int32_t kd, bool fp32, bool count)
 {
-    if (fp32) return kd == 16 ? band_kernel<16, float>(sels) : band_kernel<8, float>(sels);
-    return band_kernel<8, double>(sels);
+    if (fp32)
+        return kd == 16 ? band_kernel<16, float>(sels, count) : band_kernel<8, float>(sels, count);
+    return band_kernel<8, double>(sels, count);
 }
 
 }  // namespace
@@ -647,7 +664,7 @@ hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_la
                              int32_t grid, hipStream_t st)
 {
     if (grid <= 0 || !(sels & SEL_BAND)) return hipSuccess;
-    const void *k = band_kernel_for(sels, diags_per_lane, fp32);
+    const void *k = band_kernel_for(sels, diags_per_lane, fp32, b.visits != nullptr);
     Batch arg = b;
     void *args[] = {&arg};
     return hipLaunchKernel(k, dim3(grid), dim3(64), args, 0, st);
@@ -656,7 +673,7 @@ hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_la
 int32_t band_blocks_per_cu(uint32_t sels, int32_t diags_per_lane, bool fp32)
 {
     int nb = 0;
-    const void *k = band_kernel_for(sels, diags_per_lane, fp32);
+    const void *k = band_kernel_for(sels, diags_per_lane, fp32, false);
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }

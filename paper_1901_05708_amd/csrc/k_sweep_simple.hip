@@ -22,13 +22,15 @@ __device__ __forceinline__ double pnorm_term(double d, double p)
 }
 
 template <int KIND, int PC>
-__device__ __forceinline__ void sweep_simple(const Series &s, int32_t R)
+__device__ __forceinline__ void sweep_simple(const Series &s, int32_t R,
+                                             unsigned long long *visits)
 {
     const int64_t k = (int64_t)s.excl + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= s.N) return;
     const int64_t i0 = (int64_t)blockIdx.y * R;
     const int64_t iend = min(i0 + (int64_t)R, s.N - k);
     if (i0 >= iend) return;
+    if (visits) atomicAdd(visits, (unsigned long long)(iend - i0));   // test mode
     const unsigned long long mask = (1ull << s.gb) - 1ull;
     const int m = s.m;
     const double *ti = s.T + i0;
@@ -81,11 +83,11 @@ __global__ void k_sweep_simple(Batch b)
     const Series s = J.s;
     const int32_t R = J.seg_rows;
     switch (sel_of(s.kind, s.pclass)) {
-    case SEL_AAMP: sweep_simple<AAMP, P_TWO>(s, R); break;
-    case SEL_ACAMP: sweep_simple<ACAMP, P_TWO>(s, R); break;
-    case SEL_P1: sweep_simple<PNORM, P_ONE>(s, R); break;
-    case SEL_P3: sweep_simple<PNORM, P_THREE>(s, R); break;
-    default: sweep_simple<PNORM, P_GENERIC>(s, R); break;
+    case SEL_AAMP: sweep_simple<AAMP, P_TWO>(s, R, b.visits); break;
+    case SEL_ACAMP: sweep_simple<ACAMP, P_TWO>(s, R, b.visits); break;
+    case SEL_P1: sweep_simple<PNORM, P_ONE>(s, R, b.visits); break;
+    case SEL_P3: sweep_simple<PNORM, P_THREE>(s, R, b.visits); break;
+    default: sweep_simple<PNORM, P_GENERIC>(s, R, b.visits); break;
     }
 }
 

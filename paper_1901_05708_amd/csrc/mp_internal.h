@@ -142,6 +142,7 @@ struct Batch {
     int64_t simple_diag;       // largest diagonal count of the simple kernel's jobs
     int64_t simple_segs;       // largest segment count of the simple kernel's jobs
     Fallback fb;
+    unsigned long long *visits;    // pair-visit counter (test mode), else null
 };
 
 // Kernel selectors: which distance specialisations a launch contains.
