@@ -27,8 +27,8 @@ __device__ __forceinline__ double pn_term(double d, double p)
 template <int KIND, int PC>
 __device__ double exact_sum(const Series &s, int64_t i, int64_t j)
 {
-    const double *a = s.T + i;
-    const double *b = s.T + j;
+    const gptr<double> a = as_global(s.T) + i;
+    const gptr<double> b = as_global(s.T) + j;
     const int m = s.m;
     double acc = 0.0;
     if (KIND == ACAMP) {
@@ -66,7 +66,7 @@ __device__ __forceinline__ bool legal_pair(const Series &s, int64_t i, int64_t j
     if (j < 0 || j >= s.N) return false;
     int64_t g = i > j ? i - j : j - i;
     if (g < s.excl) return false;
-    if (s.kind == ACAMP && s.isconst[j]) return false;
+    if (s.kind == ACAMP && as_global(s.isconst)[j]) return false;
     return true;
 }
 
@@ -249,7 +249,7 @@ __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, i
         if (staged && (int64_t)r != prev_row) {
             __syncthreads();
             for (int l = lane; l < m; l += FB_WAVE)
-                q[l] = (KIND == ACAMP) ? (s.T[i + l] - mi) * ni : s.T[i + l];
+                q[l] = (KIND == ACAMP) ? (as_global(s.T)[i + l] - mi) * ni : as_global(s.T)[i + l];
             __syncthreads();
             prev_row = r;
         }
@@ -257,10 +257,11 @@ __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, i
         int qn = 0;
         // Exact score of column j. The column window is read in batches of
         // FB_UNROLL independent loads so that their latency overlaps.
+        const gptr<double> Tg = as_global(s.T);
         auto score = [&](int64_t j) {
-            const double *b = s.T + j;
-            const double mj = (KIND == ACAMP) ? s.mu[j] : 0.0;
-            const double nj = (KIND == ACAMP) ? s.invn[j] : 1.0;
+            const gptr<double> b = Tg + j;
+            const double mj = (KIND == ACAMP) ? as_global(s.mu)[j] : 0.0;
+            const double nj = (KIND == ACAMP) ? as_global(s.invn)[j] : 1.0;
             double acc = 0.0;
             auto term = [&](double a, double bv) {
                 if (KIND == ACAMP) {
@@ -275,7 +276,7 @@ __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, i
             };
             auto qa = [&](int l) {
                 if (staged) return q[l];
-                return (KIND == ACAMP) ? (s.T[i + l] - mi) * ni : s.T[i + l];
+                return (KIND == ACAMP) ? (Tg[i + l] - mi) * ni : Tg[i + l];
             };
             int l = 0;
             for (; l + FB_UNROLL <= m; l += FB_UNROLL) {
@@ -299,7 +300,8 @@ __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, i
                 // the row's own pivot distance is uniform across the wavefront
                 const float pa = fb.pd[(int64_t)k * fb.pd_stride + pd_base + i];
                 if (cand) {
-                    const double a = pa, b = fb.pd[(int64_t)k * fb.pd_stride + pd_base + j];
+                    const double a = pa,
+                                 b = as_global(fb.pd)[(int64_t)k * fb.pd_stride + pd_base + j];
                     const double lb = fabs(a - b) - FB_PD_SLACK * (a + b);
                     if (lb > thr) cand = false;       // false for NaN bounds: kept
                 }
@@ -324,7 +326,7 @@ __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, i
             const unsigned long long o = __shfl_xor(best, off);
             best = o < best ? o : best;
         }
-        if (lane == 0 && best != KEY_NONE) atomicMin(&fb.keys[r], best);
+        if (lane == 0 && best != KEY_NONE) global_min(&fb.keys[r], best);
     }
 }
 

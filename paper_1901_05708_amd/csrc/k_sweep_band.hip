@@ -241,13 +241,15 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
 #pragma unroll
     for (int d = 0; d < KD; ++d) wd[d] = (uint32_t)(lane * KD + d);
 
-    const F *sx = Streams<F>::x(s);
-    const F *sy = Streams<F>::y(s);
-    const F *sz = Streams<F>::z(s);
+    const gptr<F> sx = as_global(Streams<F>::x(s));
+    const gptr<F> sy = as_global(Streams<F>::y(s));
+    const gptr<F> sz = as_global(Streams<F>::z(s));
+    const gptr<double> Tg = as_global(s.T);
+    const gptr<double> mug = as_global(s.mu);
     cdouble *Tc = as_const(s.T);
-    const auto xc = as_const(sx);
-    const auto yc = as_const(sy);
-    const auto zc = as_const(sz);
+    const auto xc = as_const(Streams<F>::x(s));
+    const auto yc = as_const(Streams<F>::y(s));
+    const auto zc = as_const(Streams<F>::z(s));
     {
         const int nsteps = (int)(i1 - i0) - 1;      // recurrence steps after the first row
         const int64_t cb = i0 + k_lo;               // stream index of local column 0
@@ -263,16 +265,16 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
             for (int d = 0; d < KD; ++d) {
                 acc[d] = 0.0;
                 win[d] = 0.0;
-                muj[d] = (KIND == ACAMP) ? s.mu[min(jb + d, N - 1)] : 0.0;
+                muj[d] = (KIND == ACAMP) ? mug[min(jb + d, N - 1)] : 0.0;
             }
 #pragma unroll
-            for (int d = 0; d < KD - 1; ++d) win[d] = s.T[min(jb + d, tmax)];
+            for (int d = 0; d < KD - 1; ++d) win[d] = Tg[min(jb + d, tmax)];
             for (int l0 = 0; l0 < m; l0 += KD) {
 #pragma unroll
                 for (int q = 0; q < KD; ++q) {
                     const int l = l0 + q;
                     if (l < m) {
-                        win[(q + KD - 1) % KD] = s.T[min(jb + l + KD - 1, tmax)];
+                        win[(q + KD - 1) % KD] = Tg[min(jb + l + KD - 1, tmax)];
                         const double tr = Tc[i0 + l];
 #pragma unroll
                         for (int d = 0; d < KD; ++d) {
@@ -371,7 +373,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
             if ((lane & 7) == 0 && r < cnt && row < i1 && P::flushable(KIND, v)) {
                 const int64_t j = row + k_lo + (int64_t)(P::index(v) & (uint32_t)(WD - 1));
                 const unsigned long long idx = (j < N) ? (unsigned long long)j : gmask;
-                atomicMin(&s.keys[row], pack_key((double)v, idx, gmask));
+                global_min(&s.keys[row], pack_key((double)v, idx, gmask));
             }
             lds_order();
         };
@@ -384,7 +386,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 const int64_t j = cb + cend - lane;
                 if (j < N && P::flushable(KIND, v)) {
                     const int64_t i = j - k_lo - (int64_t)(P::index(v) & (uint32_t)(WD - 1));
-                    atomicMin(&s.keys[j], pack_key((double)v, (unsigned long long)i, gmask));
+                    global_min(&s.keys[j], pack_key((double)v, (unsigned long long)i, gmask));
                 }
             }
         };
@@ -519,19 +521,37 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
             const int64_t j = cb + tb + 1 + (int64_t)KD * lane + d;
             if (j < N && P::flushable(KIND, v)) {
                 const int64_t i = j - k_lo - (int64_t)(P::index(v) & (uint32_t)(WD - 1));
-                atomicMin(&s.keys[j], pack_key((double)v, (unsigned long long)i, gmask));
+                global_min(&s.keys[j], pack_key((double)v, (unsigned long long)i, gmask));
             }
         }
-        if (COUNT && visited) atomicAdd(visits, visited);
+        if (COUNT && visited) {
+            typedef __attribute__((address_space(1))) unsigned long long gu64;
+            __hip_atomic_fetch_add((gu64 *)visits, visited, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
         lds_order();
     }
+}
+
+// Resident waves per SIMD the compiler is asked for. The FP64 AAMP and
+// p-norm kernels fit 3 waves (168 VGPRs) at the cost of a few spills outside
+// the inner loop, 2-4 % faster than 2 waves; the FP64 ACAMP and mixed kernels
+// would spill inside it (ACAMP: 55 % slower) and keep the default. FP32 with 8
+// diagonals per lane fits 4 waves without spills.
+template <uint32_t SELS, int KD, typename F>
+constexpr int waves_target()
+{
+    if (KD != 8) return 1;
+    if (sizeof(F) == 4) return 4;
+    return (SELS == SEL_AAMP || SELS == SEL_P1 || SELS == SEL_P3) ? 3 : 1;
 }
 
 // The persistent sweep over every band of every job of a launch. SELS is the
 // set of distance specialisations the launch holds: a single one gets a kernel
 // of its own; a mix dispatches per item (the branch is wave-uniform).
 template <uint32_t SELS, int KD, typename F, bool COUNT>
-__global__ void __launch_bounds__(64) k_sweep_band(Batch b)
+__global__ void __launch_bounds__(64)
+    __attribute__((amdgpu_waves_per_eu(waves_target<SELS, KD, F>()))) k_sweep_band(Batch b)
 {
     constexpr int RING = 64 * KD;
     constexpr int NF = (SELS & SEL_ACAMP) ? 3 : 2;

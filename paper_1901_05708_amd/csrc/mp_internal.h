@@ -110,6 +110,25 @@ struct Job {
     int32_t seg_rows;      // rows between exact restarts (refresh interval R)
 };
 
+// Every array the kernels touch lives in device global memory. Addressing it
+// through the global address space makes the compiler emit global_* rather
+// than flat_* instructions; flat ones also count against the LDS wait
+// counter, so a wait for an LDS read would also wait for an outstanding HBM
+// load or L2 atomic.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T *p)
+{
+    return (gptr<T>)p;
+}
+
+__device__ __forceinline__ void global_min(unsigned long long *p, unsigned long long v)
+{
+    typedef __attribute__((address_space(1))) unsigned long long gu64;
+    __hip_atomic_fetch_min((gu64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Job tables are read-only during a launch: kernels read them through the
 // constant address space so that wave-uniform fields become scalar loads.
 template <class T>
