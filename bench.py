@@ -324,6 +324,20 @@ def main():
                                    "finalize": round(f32["finalize_ms"], 4)},
             "sweep_gain_vs_fp64": round(f64["sweep_ms"] / f32["sweep_ms"], 4),
         }
+    # motif / discord extraction on the headline profile (k = 10 each)
+    Pd = torch.as_tensor(f64["P"], device="cuda")
+    Id = torch.as_tensor(f64["I"], device="cuda")
+    tk = {}
+    for mode in ("motifs", "discords"):
+        mp.topk(Pd, Id, 10, h["m"], mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            mp.topk(Pd, Id, 10, h["m"], mode)
+        torch.cuda.synchronize()
+        tk[mode + "_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
+    out["topk"] = {"k": 10, "excl": h["m"], **tk,
+                   "note": "host wall time per call including the count read-back"}
     if not args.no_batch:
         out["batch"] = batch_workload(args, mp, W, torch)
     if args.copy_calib > 0:

@@ -147,6 +147,28 @@ typedef struct mp_job {
 int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
              double *P_cat, int64_t *I_cat, void *stream);
 
+/*
+ * mp_topk -- motifs or discords of a computed profile, the two uses of the
+ * matrix profile named in Sec. 1. P and I are the N outputs of one mp_aamp /
+ * mp_pnorm / mp_acamp call (device pointers).
+ *  - mode MP_MOTIFS: k times, the not yet excluded window i with the smallest
+ *    finite P[i] (ties: the smallest i) is reported as (i, I[i], P[i]), then
+ *    every window x with |x - i| < excl or |x - I[i]| < excl is excluded (a
+ *    motif pair is reported once, and its trivially shifted neighbours not).
+ *  - mode MP_DISCORDS: the largest finite P[i] instead, excluding the windows
+ *    with |x - i| < excl.
+ * out_i, out_j (int64) and out_d (double) are device arrays of k entries;
+ * *out_count (device int32) receives the number of rounds that found a
+ * candidate (fewer than k once every finite window is excluded; entries past
+ * it are left untouched). excl >= 1 (typically the profile's exclusion zone
+ * or m); 0 <= k <= 65536; 0 <= N < MP_MAX_N. Stream-ordered and
+ * asynchronous; 3 small launches per round; uses the device workspace.
+ */
+#define MP_MOTIFS 0
+#define MP_DISCORDS 1
+int mp_topk(const double *P, const int64_t *I, int64_t N, int32_t k, int32_t excl, int32_t mode,
+            int64_t *out_i, int64_t *out_j, double *out_d, int32_t *out_count, void *stream);
+
 /* Human-readable description of an error code, including the HIP error text
  * of the calling thread's last MP_EHIP. Never NULL; the string is owned by the
  * library and valid until the next call on the same thread. */

@@ -27,8 +27,9 @@ MP_FP64, MP_FP32_REFRESH = 0, 1
 KIND_AAMP, KIND_PNORM, KIND_ACAMP = 0, 1, 2
 FP32_RTOL = 1e-4
 
-EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_strerror", "mp_release",
-            "mp_set_profiling", "mp_profile_read")
+EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_topk", "mp_strerror",
+            "mp_release", "mp_set_profiling", "mp_profile_read")
+MP_MOTIFS, MP_DISCORDS = 0, 1
 
 
 class MpError(RuntimeError):
@@ -75,6 +76,8 @@ def load(path: str = LIB_PATH):
     lib.mp_batch.argtypes = [vp, ctypes.POINTER(MpJob), i32, i32, vp, vp, vp]
     for f in (lib.mp_aamp, lib.mp_pnorm, lib.mp_acamp, lib.mp_batch):
         f.restype = ctypes.c_int
+    lib.mp_topk.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.mp_topk.restype = ctypes.c_int
     lib.mp_strerror.argtypes = [ctypes.c_int]
     lib.mp_strerror.restype = ctypes.c_char_p
     lib.mp_release.argtypes = []
@@ -209,6 +212,30 @@ def batch(T_cat, jobs: Sequence[Job], precision="fp64", stream=None, out=None, t
     _check(load().mp_batch(T_cat.data_ptr(), table, len(jobs), _prec(precision),
                            P.data_ptr(), I.data_ptr(), _stream(stream)))
     return P, I
+
+
+def topk(P, I, k: int, excl: int, mode: str = "motifs", stream=None):
+    """Motifs (mode="motifs": smallest profile values, each pair once) or
+    discords (mode="discords": largest values) of a profile (P, I) computed
+    by aamp / pnorm / acamp, with exclusion zone excl (mp_topk). Returns
+    (i, j, d) tensors: window, its nearest neighbour, distance. Reads the
+    result count back, so it synchronises with the stream."""
+    import torch
+    if mode not in ("motifs", "discords"):
+        raise ValueError("mode must be 'motifs' or 'discords'")
+    if P.device.type != "cuda" or P.dtype != torch.float64 or I.dtype != torch.int64:
+        raise TypeError("P must be float64 and I int64 tensors on a HIP device")
+    P, I = P.contiguous(), I.contiguous()
+    k = int(k)
+    oi = torch.empty(max(k, 1), dtype=torch.int64, device=P.device)
+    oj = torch.empty(max(k, 1), dtype=torch.int64, device=P.device)
+    od = torch.empty(max(k, 1), dtype=torch.float64, device=P.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=P.device)
+    _check(load().mp_topk(P.data_ptr(), I.data_ptr(), P.shape[0], k, int(excl),
+                          MP_MOTIFS if mode == "motifs" else MP_DISCORDS, oi.data_ptr(),
+                          oj.data_ptr(), od.data_ptr(), cnt.data_ptr(), _stream(stream)))
+    c = int(cnt.item())
+    return oi[:c], oj[:c], od[:c]
 
 
 def release():

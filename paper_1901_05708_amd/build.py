@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmp.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "k_prep.hip", "k_sweep_simple.hip", "k_sweep_band.hip", "k_finalize.hip"]
+SOURCES = ["api.hip", "k_prep.hip", "k_sweep_simple.hip", "k_sweep_band.hip", "k_finalize.hip",
+           "k_topk.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

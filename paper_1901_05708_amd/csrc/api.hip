@@ -82,6 +82,11 @@ struct Workspace {
     int32_t *pivots1 = nullptr;
     int64_t *band1 = nullptr;
     int64_t band1_cap = 0;
+    // motif / discord extraction: exclusion mask and per-round scratch
+    uint8_t *topk_mask = nullptr;
+    int64_t topk_mask_cap = 0;
+    unsigned long long *topk_scratch = nullptr;
+    int64_t topk_scratch_cap = 0;
     uint64_t generation = 1;           // bumped whenever the arrays above move
     int arch_ok = -1;                  // -1 unknown, 0 no, 1 gfx950
     int cus = 0;
@@ -109,9 +114,13 @@ void free_arrays(Workspace &w)
 void free_ws(Workspace &w)
 {
     free_arrays(w);
-    void *ptrs[] = {w.job1, w.row_base1, w.flag1, w.pivots1, w.band1, w.visits};
+    void *ptrs[] = {w.job1, w.row_base1, w.flag1, w.pivots1, w.band1, w.visits, w.topk_mask,
+                    w.topk_scratch};
     for (void *p : ptrs) hipFree(p);
     w.visits = nullptr;
+    w.topk_mask = nullptr;
+    w.topk_scratch = nullptr;
+    w.topk_mask_cap = w.topk_scratch_cap = 0;
     w.job1 = nullptr;
     w.row_base1 = w.band1 = nullptr;
     w.flag1 = w.pivots1 = nullptr;
@@ -984,6 +993,36 @@ int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pre
              double *P_cat, int64_t *I_cat, void *stream)
 {
     return run_batch(T_cat, jobs, njobs, precision, P_cat, I_cat, stream);
+}
+
+int mp_topk(const double *P, const int64_t *I, int64_t N, int32_t k, int32_t excl, int32_t mode,
+            int64_t *out_i, int64_t *out_j, double *out_d, int32_t *out_count, void *stream)
+{
+    if (!P || !I || !out_i || !out_j || !out_d || !out_count)
+        return fail(MP_EINVAL, "null pointer argument");
+    if (N < 0 || N >= MP_MAX_N) return fail(MP_EINVAL, "N must be in [0, 2^31)");
+    if (k < 0 || k > 65536) return fail(MP_EINVAL, "k must be in [0, 65536]");
+    if (excl < 1) return fail(MP_EINVAL, "excl must be >= 1");
+    if (mode != MP_MOTIFS && mode != MP_DISCORDS)
+        return fail(MP_EINVAL, "mode must be MP_MOTIFS or MP_DISCORDS");
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    Workspace *w = nullptr;
+    int dev = 0;
+    RC_TRY(get_ws(&w, &dev));
+    if (w->topk_mask_cap < std::max<int64_t>(N, 1)) {
+        RC_TRY(grow(&w->topk_mask, (size_t)std::max<int64_t>(N, 1), "top-k mask"));
+        w->topk_mask_cap = std::max<int64_t>(N, 1);
+    }
+    const int64_t sc = 3 * (int64_t)std::max(k, 1);
+    if (w->topk_scratch_cap < sc) {
+        RC_TRY(grow(&w->topk_scratch, (size_t)sc, "top-k scratch"));
+        w->topk_scratch_cap = sc;
+    }
+    HIP_TRY(launch_topk(P, I, N, k, excl, mode, out_i, out_j, out_d, out_count, w->topk_scratch,
+                        w->topk_mask, (hipStream_t)stream),
+            "top-k launch");
+    g_last_code = MP_OK;
+    return MP_OK;
 }
 
 const char *mp_strerror(int code)

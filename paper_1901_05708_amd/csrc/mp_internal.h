@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace mpk {
 
 enum Kind : int32_t { AAMP = 0, PNORM = 1, ACAMP = 2 };
@@ -203,6 +205,13 @@ hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_la
 hipError_t launch_sweep_simple(const Batch &b, hipStream_t st);
 hipError_t launch_finalize(const Batch &b, hipStream_t st);
 hipError_t launch_fallback(const Batch &b, hipStream_t st);
+
+// Motifs / discords of a computed profile (k rounds of 3 small kernels).
+// scratch holds 3k u64, mask N bytes.
+hipError_t launch_topk(const double *P, const int64_t *I, int64_t N, int32_t k, int32_t excl,
+                       int32_t mode, int64_t *out_i, int64_t *out_j, double *out_d,
+                       int32_t *out_count, unsigned long long *scratch, uint8_t *mask,
+                       hipStream_t st);
 
 // Band-kernel facts for the planner: resident waves per CU for a selector set,
 // and the selector sets that have their own kernel (others use the mixed one).

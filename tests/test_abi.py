@@ -96,6 +96,23 @@ def test_stats_struct_matches_header():
     assert sum(sizes[t] for t, _ in fields) == ctypes.sizeof(mp.MpStats)
 
 
+def test_topk_arguments_rejected_without_gpu(lib):
+    d = ctypes.c_void_p(16)
+    ok = (d, d, 100, 5, 3, mp.MP_MOTIFS, d, d, d, d, None)
+    bad = [
+        (None,) + ok[1:],                                   # null P
+        ok[:2] + (-1,) + ok[3:],                            # N < 0
+        ok[:2] + (1 << 31,) + ok[3:],                       # N too large
+        ok[:3] + (-1,) + ok[4:],                            # k < 0
+        ok[:3] + (65537,) + ok[4:],                         # k too large
+        ok[:4] + (0,) + ok[5:],                             # excl < 1
+        ok[:5] + (2,) + ok[6:],                             # bad mode
+        ok[:9] + (None,) + ok[10:],                         # null count
+    ]
+    for args in bad:
+        assert lib.mp_topk(*args) == mp.MP_EINVAL
+
+
 def test_strerror_never_null(lib):
     for code in (0, -1, -2, -3, -4, 12345):
         assert isinstance(lib.mp_strerror(code), bytes)
