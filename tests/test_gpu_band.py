@@ -176,3 +176,20 @@ def test_band_fp32_runs_motifs_offset(mp):
         inside = np.arange(s, s + L - m + 1)
         assert np.all(np.isinf(P[inside])) and np.all(I[inside] == -1)
     info, P, I = _check32(mp, "aamp", T, m, label="fp32-offset-aamp")
+
+
+# ---- long windows: the exact restarts and the rescoring run over m >= 2048 ----
+
+@pytest.mark.parametrize("m", [2048, 4096])
+@pytest.mark.parametrize("kind", ["aamp", "acamp"])
+def test_band_long_windows(mp, kind, m):
+    rng = np.random.default_rng(m + (kind == "acamp"))
+    T = np.cumsum(rng.standard_normal(m + 3000))
+    _check(mp, kind, T, m, label=f"long-{kind}-{m}")
+    _check32(mp, kind, T, m, label=f"long-fp32-{kind}-{m}")
+
+
+def test_band_long_windows_pnorm(mp):
+    T, _ = W.sines(n=7000, m=2048)
+    _check(mp, "pnorm", T, 2048, p=3.0, label="long-p3")
+    _check(mp, "pnorm", T, 2048, p=1.0, label="long-p1")
