@@ -61,7 +61,11 @@ static int integer_p(double p)
 }
 
 /* Window mean, population standard deviation (two passes, App. A) and the
- * exact all-samples-equal flag, for every window. */
+ * exact all-samples-equal flag, for every window. The mean is evaluated as
+ * t_i + (1/m) sum_l (t_{i+l} - t_i), the same quantity as (1/m) sum_l t_{i+l}
+ * but with FP64 rounding at the scale of the window's deviations rather than
+ * of the series' offset (which matters for near-constant windows far from
+ * zero). */
 int oracle_window_stats(const double *T, int64_t n, int32_t m,
                         double *mu, double *sigma, uint8_t *isconst)
 {
@@ -71,10 +75,10 @@ int oracle_window_stats(const double *T, int64_t n, int32_t m,
         double s = 0.0;
         int c = 1;
         for (int32_t l = 0; l < m; ++l) {
-            s += T[i + l];
+            s += T[i + l] - T[i];
             if (T[i + l] != T[i]) c = 0;
         }
-        double mean = s / (double)m;
+        double mean = T[i] + s / (double)m;
         double v = 0.0;
         for (int32_t l = 0; l < m; ++l) {
             double d = T[i + l] - mean;

@@ -27,7 +27,7 @@ MUTANTS = {
     "sample_std": ("sigma[i] = sqrt(v / (double)m);", "sigma[i] = sqrt(v / (double)(m - 1));"),
     "runner_up_lost": ("            second = best;\n", ""),
     "pnorm_no_abs": ("double a = fabs(x);", "double a = x;"),
-    "wrong_mean": ("double mean = s / (double)m;", "double mean = s / (double)(m + 1);"),
+    "wrong_mean": ("double mean = T[i] + s / (double)m;", "double mean = T[i] + s / (double)(m + 1);"),
     "root_dropped": ("        if (p == 2.0) return sqrt(s);\n", "        if (p == 2.0) return s;\n"),
 }
 

@@ -424,3 +424,22 @@ def test_rejects_bad_arguments(oracle_mod):
         oracle_mod.profile(T, 5, "aamp", excl=0)
     with pytest.raises(ValueError):
         oracle_mod.profile(T, 5, "aamp", rows=[100])
+
+
+def test_znorm_affine_invariance_far_from_zero(oracle_mod):
+    """DZ is invariant under t -> a t + c (Def. 2.7). With c large against the
+    window deviations (c = 1e5, a = 1e-3, m = 128), windows at the edges of
+    constant runs are near-constant; their distances survive only if the
+    window mean is evaluated without offset-scale rounding. (A plain running
+    sum of the samples gives differences of 4.5e-6 here; the shifted sum,
+    4.7e-8.)"""
+    rng = np.random.default_rng(44)
+    T = np.cumsum(rng.standard_normal(900))
+    T[200:430] = T[200]
+    T[550:780] = T[550]
+    m, excl = 128, 32
+    P, I, Q = oracle_mod.profile(T, m, "acamp", excl=excl)
+    P2, I2, Q2 = oracle_mod.profile(1e-3 * T + 1e5, m, "acamp", excl=excl)
+    fin = np.isfinite(P)
+    assert np.array_equal(fin, np.isfinite(P2))
+    assert np.max(np.abs(P[fin] - P2[fin])) < 1e-6
