@@ -20,15 +20,20 @@ __global__ void k_window_stats(Batch b)
     if (j >= s.N) return;
     const double *w = s.T + j;
     const int m = s.m;
+    // The mean is summed around the window's first sample, so its rounding
+    // error scales with the window's deviations rather than with the series'
+    // offset. Neighbouring windows share all but one sample, so a plain sum's
+    // offset-scale errors are correlated from window to window, and the
+    // covariance recurrence would accumulate them as drift.
     double sum = 0.0;
     bool same = true;
     const double w0 = w[0];
     for (int l = 0; l < m; ++l) {
         double v = w[l];
-        sum += v;
+        sum += v - w0;
         same = same && (v == w0);
     }
-    const double mu = sum / (double)m;
+    const double mu = w0 + sum / (double)m;
     double ss = 0.0;
     for (int l = 0; l < m; ++l) {
         double d = w[l] - mu;
