@@ -247,6 +247,42 @@ def batch_workload(args, mp, W, torch):
     return res
 
 
+def incremental(mp, h, torch):
+    """Appending to the headline series (ACAMP, m = 256): the first 131072
+    samples load through the one-shot path, then single samples and chunks
+    of 256 are appended. Each new window is one new column of N pairs."""
+    import numpy as np
+    T = h["T"]
+    m = h["m"]
+    rng = np.random.default_rng(99)
+    more = T[-1] + np.cumsum(rng.standard_normal(4096 + 200))
+    inc = mp.Incremental(m, kind="acamp", capacity=len(T) + len(more))
+    inc.append(torch.as_tensor(T, device="cuda"))
+    torch.cuda.synchronize()
+    ones = [torch.as_tensor(more[k:k + 1], device="cuda") for k in range(200)]
+    chunks = [torch.as_tensor(more[200 + 256 * k:200 + 256 * (k + 1)], device="cuda")
+              for k in range(16)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in ones:
+        inc.append(c)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for c in chunks:
+        inc.append(c)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    N = inc.size()[1]
+    inc.close()
+    single = (t1 - t0) / len(ones)
+    chunk = (t2 - t1) / len(chunks)
+    return {"single_append_us": round(single * 1e6, 1),
+            "chunk256_append_ms": round(chunk * 1e3, 3),
+            "chunk256_pairs_per_s": round(256 * N / chunk / 1e9, 2),
+            "unit_note": "host wall time per append; pairs/s in G (N pairs per new window)",
+            "N": N}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -338,6 +374,7 @@ def main():
         tk[mode + "_ms"] = round((time.perf_counter() - t0) / 5 * 1e3, 3)
     out["topk"] = {"k": 10, "excl": h["m"], **tk,
                    "note": "host wall time per call including the count read-back"}
+    out["incremental"] = incremental(mp, h, torch)
     if not args.no_batch:
         out["batch"] = batch_workload(args, mp, W, torch)
     if args.copy_calib > 0:

@@ -169,6 +169,41 @@ int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pre
 int mp_topk(const double *P, const int64_t *I, int64_t N, int32_t k, int32_t excl, int32_t mode,
             int64_t *out_i, int64_t *out_j, double *out_d, int32_t *out_count, void *stream);
 
+/*
+ * Incremental profiles: the profile of a series that grows by appended
+ * samples. Appending one sample adds one window w, i.e. one new column of the
+ * distance matrix; each entry (i, w) follows from (i - 1, w - 1) in the
+ * previous column by the O(1) updates of Lemmas 1-3, so the whole profile is
+ * brought up to date in O(N) per added window. Every row whose minimum
+ * improves, and every new window, is rescored exactly in FP64, so after any
+ * sequence of appends (P, I) is what mp_aamp / mp_pnorm / mp_acamp in FP64
+ * would return for the whole series (up to ties). The carried column is
+ * recomputed exactly every `refresh` added windows (0: 4096). The first
+ * windows, and any append adding more than max(2048, N/8) windows, run the
+ * one-shot FP64 pipeline instead.
+ *
+ * mp_inc_create: m, kind (MP_KIND_*), p, excl (<= 0: ceil(m/4)) as for the
+ *   single-series calls; capacity = the largest number of samples the series
+ *   will hold (m <= capacity < MP_MAX_N; device buffers of about 70 bytes
+ *   per sample are allocated now). *out receives the handle.
+ * mp_inc_append: appends count samples from the DEVICE pointer T (copied).
+ *   MP_EINVAL if the capacity would be exceeded. Stream-ordered and
+ *   asynchronous; calls on one handle must be serialised on one stream.
+ * mp_inc_state: the current number of samples and windows, and DEVICE
+ *   pointers to the N profile values and indices (owned by the handle, valid
+ *   until mp_inc_destroy; read them after the stream has synchronised).
+ * mp_inc_read: copies the current N profile values and indices into the
+ *   caller's DEVICE arrays, stream-ordered.
+ * mp_inc_destroy: waits for the device and frees the handle.
+ */
+typedef struct mp_inc mp_inc;
+int mp_inc_create(int32_t m, int32_t kind, double p, int32_t excl, int64_t capacity,
+                  int32_t refresh, mp_inc **out);
+int mp_inc_append(mp_inc *h, const double *T, int64_t count, void *stream);
+int mp_inc_state(mp_inc *h, int64_t *n, int64_t *N, double **P, int64_t **I);
+int mp_inc_read(mp_inc *h, double *P, int64_t *I, void *stream);
+void mp_inc_destroy(mp_inc *h);
+
 /* Human-readable description of an error code, including the HIP error text
  * of the calling thread's last MP_EHIP. Never NULL; the string is owned by the
  * library and valid until the next call on the same thread. */

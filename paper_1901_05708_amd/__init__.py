@@ -27,7 +27,8 @@ MP_FP64, MP_FP32_REFRESH = 0, 1
 KIND_AAMP, KIND_PNORM, KIND_ACAMP = 0, 1, 2
 FP32_RTOL = 1e-4
 
-EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_topk", "mp_strerror",
+EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_topk", "mp_inc_create",
+            "mp_inc_append", "mp_inc_state", "mp_inc_read", "mp_inc_destroy", "mp_strerror",
             "mp_release", "mp_set_profiling", "mp_profile_read")
 MP_MOTIFS, MP_DISCORDS = 0, 1
 
@@ -78,6 +79,16 @@ def load(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.mp_topk.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
     lib.mp_topk.restype = ctypes.c_int
+    lib.mp_inc_create.argtypes = [i32, i32, dbl, i32, i64, i32, ctypes.POINTER(vp)]
+    lib.mp_inc_create.restype = ctypes.c_int
+    lib.mp_inc_append.argtypes = [vp, vp, i64, vp]
+    lib.mp_inc_append.restype = ctypes.c_int
+    lib.mp_inc_state.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp]
+    lib.mp_inc_state.restype = ctypes.c_int
+    lib.mp_inc_read.argtypes = [vp, vp, vp, vp]
+    lib.mp_inc_read.restype = ctypes.c_int
+    lib.mp_inc_destroy.argtypes = [vp]
+    lib.mp_inc_destroy.restype = None
     lib.mp_strerror.argtypes = [ctypes.c_int]
     lib.mp_strerror.restype = ctypes.c_char_p
     lib.mp_release.argtypes = []
@@ -236,6 +247,60 @@ def topk(P, I, k: int, excl: int, mode: str = "motifs", stream=None):
                           oj.data_ptr(), od.data_ptr(), cnt.data_ptr(), _stream(stream)))
     c = int(cnt.item())
     return oi[:c], oj[:c], od[:c]
+
+
+class Incremental:
+    """Profile of a growing series (mp_inc_*): append samples, read the
+    profile of everything appended so far.
+
+        inc = Incremental(m=64, kind="acamp", capacity=1 << 20)
+        inc.append(chunk)            # float64 HIP tensor
+        P, I = inc.profile()
+    """
+
+    _KINDS = {"aamp": KIND_AAMP, "pnorm": KIND_PNORM, "acamp": KIND_ACAMP}
+
+    def __init__(self, m: int, kind: str = "aamp", p: float = 2.0, excl: Optional[int] = None,
+                 capacity: int = 1 << 20, refresh: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.mp_inc_create(int(m), self._KINDS[kind], float(p), int(excl or 0),
+                                 int(capacity), int(refresh), ctypes.byref(h)))
+        self._h = h
+        self.m = m
+
+    def append(self, T, stream=None):
+        import torch
+        if not isinstance(T, torch.Tensor) or T.device.type != "cuda" or T.dtype != torch.float64:
+            raise TypeError("T must be a float64 tensor on a HIP device")
+        T = T.contiguous().view(-1)
+        _check(load().mp_inc_append(self._h, T.data_ptr(), T.numel(), _stream(stream)))
+
+    def size(self):
+        n, N = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().mp_inc_state(self._h, ctypes.byref(n), ctypes.byref(N), None, None))
+        return n.value, N.value
+
+    def profile(self, stream=None):
+        """(P, I) of the series appended so far, as new tensors."""
+        import torch
+        n, N = self.size()
+        P = torch.empty(max(N, 0), dtype=torch.float64, device="cuda")
+        I = torch.empty(max(N, 0), dtype=torch.int64, device="cuda")
+        if N > 0:
+            _check(load().mp_inc_read(self._h, P.data_ptr(), I.data_ptr(), _stream(stream)))
+        return P, I
+
+    def close(self):
+        if self._h:
+            load().mp_inc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release():

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libmp.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "k_prep.hip", "k_sweep_simple.hip", "k_sweep_band.hip", "k_finalize.hip",
-           "k_topk.hip"]
+           "k_topk.hip", "k_incremental.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -971,6 +971,18 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
 
 }  // namespace
 
+// Hooks for the other host files of the library (incremental profiles).
+namespace mpk {
+int report_error(int code, const char *what) { return fail(code, what); }
+int report_hip(hipError_t e, const char *where) { return fail_hip(e, where); }
+void report_ok() { g_last_code = MP_OK; }
+int profile_once(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
+                 int32_t R, double *P, int64_t *I, hipStream_t st)
+{
+    return run_series(T, n, m, kind, p, excl, MP_FP64, R, P, I, (void *)st);
+}
+}  // namespace mpk
+
 extern "C" {
 
 int mp_aamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precision, int32_t R,

@@ -213,6 +213,15 @@ hipError_t launch_topk(const double *P, const int64_t *I, int64_t N, int32_t k, 
                        int32_t *out_count, unsigned long long *scratch, uint8_t *mask,
                        hipStream_t st);
 
+// Host hooks of api.hip for the other host files: error reporting (the
+// thread's last error, read by mp_strerror), a one-shot FP64 profile through
+// the normal pipeline, and the library lock.
+int report_error(int code, const char *what);
+int report_hip(hipError_t e, const char *where);
+void report_ok();
+int profile_once(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
+                 int32_t R, double *P, int64_t *I, hipStream_t st);
+
 // Band-kernel facts for the planner: resident waves per CU for a selector set,
 // and the selector sets that have their own kernel (others use the mixed one).
 int32_t band_blocks_per_cu(uint32_t sels, int32_t diags_per_lane, bool fp32);

@@ -113,6 +113,24 @@ def test_topk_arguments_rejected_without_gpu(lib):
         assert lib.mp_topk(*args) == mp.MP_EINVAL
 
 
+def test_incremental_arguments_rejected_without_gpu(lib):
+    h = ctypes.c_void_p()
+    bad = [
+        (0, mp.KIND_AAMP, 2.0, 0, 1000, 0),        # m < 1
+        (16, 7, 2.0, 0, 1000, 0),                  # bad kind
+        (16, mp.KIND_PNORM, 0.5, 0, 1000, 0),      # p < 1
+        (16, mp.KIND_AAMP, 2.0, 0, 8, 0),          # capacity < m
+        (16, mp.KIND_AAMP, 2.0, 0, 1 << 31, 0),    # capacity too large
+        (16, mp.KIND_AAMP, 2.0, 0, 1000, -1),      # refresh < 0
+    ]
+    for args in bad:
+        assert lib.mp_inc_create(*args, ctypes.byref(h)) == mp.MP_EINVAL
+    assert lib.mp_inc_create(16, mp.KIND_AAMP, 2.0, 0, 1000, 0, None) == mp.MP_EINVAL
+    assert lib.mp_inc_append(None, ctypes.c_void_p(16), 10, None) == mp.MP_EINVAL
+    assert lib.mp_inc_read(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == mp.MP_EINVAL
+    lib.mp_inc_destroy(None)                       # a no-op
+
+
 def test_strerror_never_null(lib):
     for code in (0, -1, -2, -3, -4, 12345):
         assert isinstance(lib.mp_strerror(code), bytes)
