@@ -217,13 +217,23 @@ struct Streams<float> {
     __device__ static const float *z(const Series &s) { return s.zf; }
 };
 
+// LDS doubles the first-row staging uses: the column samples of a 64-step
+// chunk (64 KD + 64, one pad slot per KD) followed by its 64 row samples.
+template <int KD>
+constexpr int stage_doubles()
+{
+    return (64 * KD + 64) + (64 * KD + 64) / KD + 64;
+}
+
 }  // namespace
 
 // One work item: the diagonals [k_lo, k_lo + 64 KD) of series s, rows
-// [i0, i1). ring (NF x RING entries) and rowbuf (NRB x 64) are the wave's LDS.
+// [i0, i1). ring (NF x RING entries) and rowbuf (NRB x 64) are the wave's LDS;
+// stage (stage_doubles<KD>() entries) overlays them while the first row is
+// computed.
 template <int KIND, int PC, int KD, typename F, bool COUNT>
 __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, const int64_t i0,
-                                          const int64_t i1, F *ring, F *rowbuf,
+                                          const int64_t i1, F *ring, F *rowbuf, double *stage,
                                           unsigned long long *visits)
 {
     typedef Prec<F> P;
@@ -255,8 +265,21 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         const int64_t cb = i0 + k_lo;               // stream index of local column 0
 
         // ---- exact FP64 start values of the first row (the refresh) ----------
+        // At step l lane l' needs the samples t[jb + l + d], d < KD, of its
+        // diagonals and the row sample t[i0 + l]. Over a chunk of LCH steps the
+        // 64 lanes' column samples form one contiguous run, so each chunk is
+        // staged in LDS with coalesced loads (the next chunk's loads are issued
+        // before the current chunk is consumed) and each lane then reads the
+        // one sample that enters its register window per step. Column element
+        // e of a chunk sits at e + e / KD: the lanes' reads (KD elements apart)
+        // then hit distinct banks. The sums are taken in the same order as a
+        // plain loop over l.
         F S[KD];
         {
+            constexpr int LCH = 64;                     // steps per staged chunk
+            constexpr int CSPAN = WD + LCH;             // column samples per chunk
+            constexpr int NLD = CSPAN / 64;             // loads per lane per chunk
+            constexpr int ROW_OFF = CSPAN + CSPAN / KD; // row samples follow
             const int64_t jb = cb + (int64_t)KD * lane;   // this lane's first column
             const int64_t tmax = s.n - 1;
             double acc[KD], win[KD], muj[KD];
@@ -267,30 +290,60 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 win[d] = 0.0;
                 muj[d] = (KIND == ACAMP) ? mug[min(jb + d, N - 1)] : 0.0;
             }
+            auto spos = [](int e) { return e + (e >> Log2<KD>::v); };
+            double nc[NLD], nr;
+            auto fetch = [&](int l0) {
 #pragma unroll
-            for (int d = 0; d < KD - 1; ++d) win[d] = Tg[min(jb + d, tmax)];
-            for (int l0 = 0; l0 < m; l0 += KD) {
+                for (int q = 0; q < NLD; ++q) nc[q] = Tg[min(cb + l0 + 64 * q + lane, tmax)];
+                nr = Tg[min(i0 + l0 + lane, tmax)];
+            };
+            auto put = [&]() {
+                lds_order();
 #pragma unroll
-                for (int q = 0; q < KD; ++q) {
-                    const int l = l0 + q;
-                    if (l < m) {
-                        win[(q + KD - 1) % KD] = Tg[min(jb + l + KD - 1, tmax)];
-                        const double tr = Tc[i0 + l];
+                for (int q = 0; q < NLD; ++q) stage[spos(64 * q + lane)] = nc[q];
+                stage[ROW_OFF + lane] = nr;
+                lds_order();
+            };
+            fetch(0);
+            put();
 #pragma unroll
-                        for (int d = 0; d < KD; ++d) {
-                            const double wv = win[(q + d) % KD];
-                            if (KIND == AAMP) {
-                                const double e = tr - wv;
-                                acc[d] = fma(e, e, acc[d]);
-                            } else if (KIND == PNORM) {
-                                acc[d] += pw<PC, double>(tr - wv);
-                            } else {
-                                acc[d] = fma(tr - mui, wv - muj[d], acc[d]);
-                            }
-                        }
+            for (int d = 0; d < KD - 1; ++d) win[d] = stage[spos(KD * lane + d)];
+            // step l of the current chunk; q = l % KD names the register slots
+            auto step = [&](int l, int q) {
+                win[(q + KD - 1) % KD] = stage[spos(KD * lane + l + KD - 1)];
+                const double tr = stage[ROW_OFF + l];
+#pragma unroll
+                for (int d = 0; d < KD; ++d) {
+                    const double wv = win[(q + d) % KD];
+                    if (KIND == AAMP) {
+                        const double e = tr - wv;
+                        acc[d] = fma(e, e, acc[d]);
+                    } else if (KIND == PNORM) {
+                        acc[d] += pw<PC, double>(tr - wv);
+                    } else {
+                        acc[d] = fma(tr - mui, wv - muj[d], acc[d]);
                     }
                 }
+            };
+            for (int l0 = 0; l0 < m; l0 += LCH) {
+                const bool more = l0 + LCH < m;
+                if (more) fetch(l0 + LCH);
+                const int steps = min(LCH, m - l0);
+                const int full = steps & ~(KD - 1);
+                for (int g = 0; g < full; g += KD) {
+#pragma unroll
+                    for (int q = 0; q < KD; ++q) step(g + q, q);
+                }
+                if (full < steps) {
+#pragma unroll
+                    for (int q = 0; q < KD - 1; ++q)
+                        if (full + q < steps) step(full + q, q);
+                }
+                // a full chunk leaves the window slots aligned with the next
+                // chunk's first step; its entries are already in registers
+                if (more) put();
             }
+            lds_order();
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
                 const bool valid = (jb + d) <= N - 1;
@@ -555,8 +608,12 @@ __global__ void __launch_bounds__(64)
 {
     constexpr int RING = 64 * KD;
     constexpr int NF = (SELS & SEL_ACAMP) ? 3 : 2;
-    __shared__ F ring[NF * RING];
-    __shared__ F rowbuf[NRB * 64];
+    constexpr int SWEEP_D = (int)(((NF * RING + NRB * 64) * sizeof(F) + 7) / 8);
+    constexpr int LDS_D = SWEEP_D > stage_doubles<KD>() ? SWEEP_D : stage_doubles<KD>();
+    __shared__ double lds[LDS_D];
+    F *ring = reinterpret_cast<F *>(lds);
+    F *rowbuf = ring + NF * RING;
+    double *stage = lds;
 
     cint64 *row_base = as_const(b.row_base);
     cint64 *band_start = as_const(b.band_start);
@@ -601,13 +658,13 @@ __global__ void __launch_bounds__(64)
         pos += seg;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
-            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
+            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
-            band_item<ACAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
+            band_item<ACAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_P1) && sel == SEL_P1)
-            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
+            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
-            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, b.visits);
+            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
     }
 }
 
