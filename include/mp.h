@@ -34,7 +34,8 @@
  *  - R is the refresh interval (rows between exact FP64 restarts of the
  *    recurrence). R = 0 lets the library choose: the first call with a given
  *    series shape (n, m, distance, excl, precision) times a few candidate
- *    refresh intervals and band widths on the call's own input, on a library
+ *    refresh intervals, band widths and (for long windows) grid sizes on the
+ *    call's own input, on a library
  *    stream ordered after the caller's stream, and caches the fastest (this
  *    first call blocks the host until the trials end; mp_stats.ms_autotune
  *    reports their time). Set R > 0 to skip the trials.
@@ -136,8 +137,9 @@ typedef struct mp_job {
  *
  * The first call with a given batch shape (the job table without its offsets,
  * and the precision) runs the autotuner: a few trial runs of the whole batch
- * with different band widths (diagonals per lane) and refresh intervals R
- * (jobs with R = 0 only), keeping the fastest; its time is reported in
+ * with different band widths (diagonals per lane), refresh intervals R (jobs
+ * with R = 0 only) and, for long windows, persistent grid sizes, keeping the
+ * fastest; its time is reported in
  * mp_stats.ms_autotune. The first call with a given job table, precision and
  * pointers captures the pipeline into a HIP graph; later identical calls
  * replay it (while profiling is on the pipeline is launched directly, so that

@@ -323,21 +323,32 @@ int check_precision(int32_t precision)
 }
 
 // Shape knobs of a launch: diagonals per lane (band width / 64), the refresh
-// interval of jobs that leave R to the library (0: per-distance default) and
-// the persistent grid as a multiple of the resident waves.
+// interval of jobs that leave R to the library (0: per-distance default), the
+// persistent grid as a multiple of the resident waves, and a cap on the waves
+// per SIMD of the grid (0: every resident slot).
 struct Tuning {
     int32_t kd = 8;
     int32_t R = 0;
     int32_t grid_mult = 1;
+    int32_t wps = 0;
 };
 
-// Default refresh intervals. In FP64, R up to 4096 keeps drift far below the
-// 1e-9 bound even on offset, low-variance windows (at 16384 it did not), and
-// R only trades the restart cost (2m per diagonal) against item count. In FP32 every step can add 2^-24 relative error; the values
-// below minimise sweep plus exact-search time on the series shapes measured.
-int32_t default_R(uint32_t sel, bool fp32)
+// Longest FP64 refresh interval per window length. A step's rounding error is
+// relative to the per-sample scale of the streams (offset, low-variance
+// windows are the hard case), while the quantity it perturbs grows with m, so
+// the drift after R steps falls with m at a fixed R / m. 16 is the ratio of
+// R = 4096 at m = 256; with window means summed around each window's first
+// sample, affine copies with offset / scale = 1e6 showed no drift beyond the
+// 1e-9 bound up to R / m = 256, so the cap leaves a wide margin.
+constexpr int64_t FP64_R_PER_M = 16;
+
+// Default refresh intervals. In FP64, 4096, or 16 m for long windows: R only
+// trades the restart cost (2m per diagonal) against item count. In FP32 every
+// step can add 2^-24 relative error; the values below minimise sweep plus
+// exact-search time on the series shapes measured.
+int32_t default_R(uint32_t sel, bool fp32, int32_t m)
 {
-    if (!fp32) return 4096;
+    if (!fp32) return (int32_t)std::min<int64_t>(std::max<int64_t>(4096, FP64_R_PER_M * m), 1 << 24);
     switch (sel) {
     case SEL_ACAMP: return 512;
     case SEL_P1: return 1024;
@@ -447,7 +458,8 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         int64_t rows = 0, nb = 0;
         if (band) {
             rows = band_rows_total(s.N, s.excl, W, &nb);
-            int64_t R = sp.R > 0 ? sp.R : (tu.R > 0 && s.fp32 == want32 ? tu.R : default_R(sel, s.fp32));
+            int64_t R = sp.R > 0 ? sp.R
+                                 : (tu.R > 0 && s.fp32 == want32 ? tu.R : default_R(sel, s.fp32, s.m));
             j.seg_rows = (int32_t)std::min<int64_t>(R, INT32_MAX / 2);
             if (L.R_report == 0) L.R_report = j.seg_rows;
         } else if (ndiag > 0) {
@@ -501,7 +513,8 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         Group &g = L.g[c];
         if (!g.count || !g.rows) continue;
         const int32_t gkd = c == 1 ? kd : 8;
-        const int64_t slots = (int64_t)w.cus * band_blocks_per_cu(g.sels, gkd, c == 1);
+        int64_t slots = (int64_t)w.cus * band_blocks_per_cu(g.sels, gkd, c == 1);
+        if (tu.wps > 0) slots = std::min<int64_t>(slots, (int64_t)w.cus * 4 * tu.wps);
         // at least 64 rows per wave
         g.grid = (int32_t)std::max<int64_t>(
             1, std::min<int64_t>(slots * std::max(1, tu.grid_mult), g.rows / 64));
@@ -704,17 +717,23 @@ int upload_tables(const Layout &L, Tables *t)
 }
 
 // Candidate shapes of the autotuner: band width (diagonals per lane; 16 only
-// fits the register file in FP32) times refresh interval.
-std::vector<Tuning> tune_candidates(int32_t precision)
+// fits the register file in FP32) times refresh interval. In FP64 the interval
+// stays within FP64_R_PER_M times the shortest window of the launch; long
+// windows also try grids of one or two waves per SIMD, since every wave pays
+// at least one O(m) restart.
+std::vector<Tuning> tune_candidates(int32_t precision, int32_t m_min)
 {
     std::vector<Tuning> c;
     if (precision == MP_FP32_REFRESH) {
         for (int kd : {8, 16})
-            for (int R : {256, 512, 1024, 2048}) c.push_back(Tuning{kd, R, 1});
+            for (int R : {256, 512, 1024, 2048}) c.push_back(Tuning{kd, R, 1, 0});
     } else {
-        // FP64 drift grows with R (on offset, low-variance data it reached
-        // 1e-4 relative at R = 16384); 4096 keeps it far below 1e-9
-        for (int R : {1024, 2048, 4096}) c.push_back(Tuning{8, R, 1});
+        for (int R : {1024, 2048, 4096}) c.push_back(Tuning{8, R, 1, 0});
+        const int64_t rmax = std::min<int64_t>(FP64_R_PER_M * m_min, 1 << 24);
+        if (rmax / 2 > 4096) c.push_back(Tuning{8, (int32_t)(rmax / 2), 1, 0});
+        if (rmax > 4096) c.push_back(Tuning{8, (int32_t)rmax, 1, 0});
+        if (m_min >= 2048)
+            for (int wps : {1, 2}) c.push_back(Tuning{8, (int32_t)rmax, 1, wps});
     }
     return c;
 }
@@ -768,7 +787,9 @@ int autotune(const std::vector<Spec> &specs, int32_t precision, Workspace &w, hi
     }
     float best_ms = -1.0f;
     int rc = MP_OK;
-    for (const Tuning &tu : tune_candidates(precision)) {
+    int32_t m_min = INT32_MAX;
+    for (const Spec &sp : specs) m_min = std::min(m_min, sp.m);
+    for (const Tuning &tu : tune_candidates(precision, m_min)) {
         float ms = 0.0f;
         if ((rc = time_candidate(specs, precision, tu, w, ls, e0, e1, &ms))) break;
         if (best_ms < 0.0f || ms < best_ms) {

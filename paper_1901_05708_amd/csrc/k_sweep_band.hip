@@ -218,11 +218,11 @@ struct Streams<float> {
 };
 
 // LDS doubles the first-row staging uses: the column samples of a 64-step
-// chunk (64 KD + 64, one pad slot per KD) followed by its 64 row samples.
+// chunk (64 KD + 64, one pad slot per KD).
 template <int KD>
 constexpr int stage_doubles()
 {
-    return (64 * KD + 64) + (64 * KD + 64) / KD + 64;
+    return (64 * KD + 64) + (64 * KD + 64) / KD;
 }
 
 }  // namespace
@@ -269,17 +269,16 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         // diagonals and the row sample t[i0 + l]. Over a chunk of LCH steps the
         // 64 lanes' column samples form one contiguous run, so each chunk is
         // staged in LDS with coalesced loads (the next chunk's loads are issued
-        // before the current chunk is consumed) and each lane then reads the
-        // one sample that enters its register window per step. Column element
-        // e of a chunk sits at e + e / KD: the lanes' reads (KD elements apart)
-        // then hit distinct banks. The sums are taken in the same order as a
-        // plain loop over l.
+        // before the current chunk is consumed); a lane then reads the KD
+        // samples entering its register window over the next KD steps at once,
+        // and the row samples arrive as scalar loads. Column element e of a
+        // chunk sits at e + e / KD, so the lanes' reads (KD elements apart) hit
+        // distinct banks. The sums are taken in the same order as a plain loop
+        // over l.
         F S[KD];
         {
             constexpr int LCH = 64;                     // steps per staged chunk
-            constexpr int CSPAN = WD + LCH;             // column samples per chunk
-            constexpr int NLD = CSPAN / 64;             // loads per lane per chunk
-            constexpr int ROW_OFF = CSPAN + CSPAN / KD; // row samples follow
+            constexpr int NLD = (WD + LCH) / 64;        // loads per lane per chunk
             const int64_t jb = cb + (int64_t)KD * lane;   // this lane's first column
             const int64_t tmax = s.n - 1;
             double acc[KD], win[KD], muj[KD];
@@ -291,38 +290,42 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 muj[d] = (KIND == ACAMP) ? mug[min(jb + d, N - 1)] : 0.0;
             }
             auto spos = [](int e) { return e + (e >> Log2<KD>::v); };
-            double nc[NLD], nr;
+            double nc[NLD];
             auto fetch = [&](int l0) {
 #pragma unroll
                 for (int q = 0; q < NLD; ++q) nc[q] = Tg[min(cb + l0 + 64 * q + lane, tmax)];
-                nr = Tg[min(i0 + l0 + lane, tmax)];
             };
             auto put = [&]() {
                 lds_order();
 #pragma unroll
                 for (int q = 0; q < NLD; ++q) stage[spos(64 * q + lane)] = nc[q];
-                stage[ROW_OFF + lane] = nr;
                 lds_order();
             };
             fetch(0);
             put();
 #pragma unroll
             for (int d = 0; d < KD - 1; ++d) win[d] = stage[spos(KD * lane + d)];
-            // step l of the current chunk; q = l % KD names the register slots
-            auto step = [&](int l, int q) {
-                win[(q + KD - 1) % KD] = stage[spos(KD * lane + l + KD - 1)];
-                const double tr = stage[ROW_OFF + l];
+            // One step: w enters slot (q + KD - 1) % KD, q = l % KD. The KD
+            // differences are formed before any of them is accumulated (the
+            // scheduling barrier keeps them apart); otherwise the compiler
+            // reuses one register for all of them and the step becomes a
+            // single chain of dependent FP64 operations.
+            auto step = [&](int q, double w, double tr) {
+                win[(q + KD - 1) % KD] = w;
+                double e[KD];
 #pragma unroll
                 for (int d = 0; d < KD; ++d) {
                     const double wv = win[(q + d) % KD];
-                    if (KIND == AAMP) {
-                        const double e = tr - wv;
-                        acc[d] = fma(e, e, acc[d]);
-                    } else if (KIND == PNORM) {
-                        acc[d] += pw<PC, double>(tr - wv);
-                    } else {
-                        acc[d] = fma(tr - mui, wv - muj[d], acc[d]);
-                    }
+                    if (KIND == ACAMP) e[d] = wv - muj[d];
+                    else e[d] = tr - wv;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                const double trc = (KIND == ACAMP) ? tr - mui : 0.0;
+#pragma unroll
+                for (int d = 0; d < KD; ++d) {
+                    if (KIND == AAMP) acc[d] = fma(e[d], e[d], acc[d]);
+                    else if (KIND == PNORM) acc[d] += pw<PC, double>(e[d]);
+                    else acc[d] = fma(trc, e[d], acc[d]);
                 }
             };
             for (int l0 = 0; l0 < m; l0 += LCH) {
@@ -331,13 +334,20 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 const int steps = min(LCH, m - l0);
                 const int full = steps & ~(KD - 1);
                 for (int g = 0; g < full; g += KD) {
+                    double nw[KD], rv[KD];
+                    const int64_t rb = uniform64(i0 + l0 + g);
 #pragma unroll
-                    for (int q = 0; q < KD; ++q) step(g + q, q);
+                    for (int q = 0; q < KD; ++q) nw[q] = stage[spos(KD * lane + g + q + KD - 1)];
+#pragma unroll
+                    for (int q = 0; q < KD; ++q) rv[q] = Tc[rb + q];
+#pragma unroll
+                    for (int q = 0; q < KD; ++q) step(q, nw[q], rv[q]);
                 }
                 if (full < steps) {
 #pragma unroll
                     for (int q = 0; q < KD - 1; ++q)
-                        if (full + q < steps) step(full + q, q);
+                        if (full + q < steps)
+                            step(q, stage[spos(KD * lane + full + q + KD - 1)], Tc[i0 + l0 + full + q]);
                 }
                 // a full chunk leaves the window slots aligned with the next
                 // chunk's first step; its entries are already in registers
