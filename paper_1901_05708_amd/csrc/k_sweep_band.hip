@@ -264,7 +264,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         const int nsteps = (int)(i1 - i0) - 1;      // recurrence steps after the first row
         const int64_t cb = i0 + k_lo;               // stream index of local column 0
 
-        // ---- exact FP64 start values of the first row (the refresh) ----------
+        // ---- FP64 start values of the first row (the refresh) ---------------
         // At step l lane l' needs the samples t[jb + l + d], d < KD, of its
         // diagonals and the row sample t[i0 + l]. Over a chunk of LCH steps the
         // 64 lanes' column samples form one contiguous run, so each chunk is
@@ -273,21 +273,30 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         // samples entering its register window over the next KD steps at once,
         // and the row samples arrive as scalar loads. Column element e of a
         // chunk sits at e + e / KD, so the lanes' reads (KD elements apart) hit
-        // distinct banks. The sums are taken in the same order as a plain loop
-        // over l.
+        // distinct banks.
+        //
+        // Euclidean and z-normalized distances need one FMA per sample and
+        // diagonal: with every sample shifted by c = t[i0] (u = t - c),
+        //   S(i0, j)   = sum u_i^2 + sum u_j^2 - 2 sum u_i u_j
+        //   cov(i0, j) = sum u_i u_j - m (mu_i0 - c)(mu_j - c)
+        // (the shift cancels in both). The column energies follow from the
+        // lane's first one by sliding the window. Rounding is relative to the
+        // windows' spread around c rather than to the series' offset. The
+        // p-norms sum |t_i - t_j|^p directly.
         F S[KD];
         {
             constexpr int LCH = 64;                     // steps per staged chunk
             constexpr int NLD = (WD + LCH) / 64;        // loads per lane per chunk
+            constexpr bool DOT = KIND != PNORM;
             const int64_t jb = cb + (int64_t)KD * lane;   // this lane's first column
             const int64_t tmax = s.n - 1;
-            double acc[KD], win[KD], muj[KD];
-            const double mui = (KIND == ACAMP) ? as_const(s.mu)[i0] : 0.0;
+            const double c0 = DOT ? Tc[i0] : 0.0;
+            double acc[KD], win[KD];
+            double erow = 0.0, ecol = 0.0;   // AAMP: sum u^2 of the row window and of column jb
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
                 acc[d] = 0.0;
                 win[d] = 0.0;
-                muj[d] = (KIND == ACAMP) ? mug[min(jb + d, N - 1)] : 0.0;
             }
             auto spos = [](int e) { return e + (e >> Log2<KD>::v); };
             double nc[NLD];
@@ -298,34 +307,33 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
             auto put = [&]() {
                 lds_order();
 #pragma unroll
-                for (int q = 0; q < NLD; ++q) stage[spos(64 * q + lane)] = nc[q];
+                for (int q = 0; q < NLD; ++q) stage[spos(64 * q + lane)] = nc[q] - c0;
                 lds_order();
             };
             fetch(0);
             put();
 #pragma unroll
             for (int d = 0; d < KD - 1; ++d) win[d] = stage[spos(KD * lane + d)];
-            // One step: w enters slot (q + KD - 1) % KD, q = l % KD. The KD
-            // differences are formed before any of them is accumulated (the
-            // scheduling barrier keeps them apart); otherwise the compiler
-            // reuses one register for all of them and the step becomes a
-            // single chain of dependent FP64 operations.
+            // One step: w enters slot (q + KD - 1) % KD, q = l % KD; tr is the
+            // (shifted) row sample.
             auto step = [&](int q, double w, double tr) {
                 win[(q + KD - 1) % KD] = w;
-                double e[KD];
+                if (DOT) {
 #pragma unroll
-                for (int d = 0; d < KD; ++d) {
-                    const double wv = win[(q + d) % KD];
-                    if (KIND == ACAMP) e[d] = wv - muj[d];
-                    else e[d] = tr - wv;
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                const double trc = (KIND == ACAMP) ? tr - mui : 0.0;
+                    for (int d = 0; d < KD; ++d) acc[d] = fma(tr, win[(q + d) % KD], acc[d]);
+                    if (KIND == AAMP) {
+                        erow = fma(tr, tr, erow);
+                        ecol = fma(win[q % KD], win[q % KD], ecol);
+                    }
+                } else {
+                    // the KD differences are formed before any is accumulated,
+                    // so that they do not share one register
+                    double e[KD];
 #pragma unroll
-                for (int d = 0; d < KD; ++d) {
-                    if (KIND == AAMP) acc[d] = fma(e[d], e[d], acc[d]);
-                    else if (KIND == PNORM) acc[d] += pw<PC, double>(e[d]);
-                    else acc[d] = fma(trc, e[d], acc[d]);
+                    for (int d = 0; d < KD; ++d) e[d] = tr - win[(q + d) % KD];
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int d = 0; d < KD; ++d) acc[d] += pw<PC, double>(e[d]);
                 }
             };
             for (int l0 = 0; l0 < m; l0 += LCH) {
@@ -339,7 +347,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
 #pragma unroll
                     for (int q = 0; q < KD; ++q) nw[q] = stage[spos(KD * lane + g + q + KD - 1)];
 #pragma unroll
-                    for (int q = 0; q < KD; ++q) rv[q] = Tc[rb + q];
+                    for (int q = 0; q < KD; ++q) rv[q] = Tc[rb + q] - c0;
 #pragma unroll
                     for (int q = 0; q < KD; ++q) step(q, nw[q], rv[q]);
                 }
@@ -347,13 +355,31 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
 #pragma unroll
                     for (int q = 0; q < KD - 1; ++q)
                         if (full + q < steps)
-                            step(q, stage[spos(KD * lane + full + q + KD - 1)], Tc[i0 + l0 + full + q]);
+                            step(q, stage[spos(KD * lane + full + q + KD - 1)],
+                                 Tc[i0 + l0 + full + q] - c0);
                 }
                 // a full chunk leaves the window slots aligned with the next
                 // chunk's first step; its entries are already in registers
                 if (more) put();
             }
             lds_order();
+            if (KIND == AAMP) {
+                // column window jb + d drops sample jb + d - 1, takes jb + d - 1 + m
+                double ec = ecol;
+#pragma unroll
+                for (int d = 0; d < KD; ++d) {
+                    if (d > 0) {
+                        const double uo = Tg[min(jb + d - 1, tmax)] - c0;
+                        const double un = Tg[min(jb + d - 1 + m, tmax)] - c0;
+                        ec = fma(un, un, fma(-uo, uo, ec));
+                    }
+                    acc[d] = fma(-2.0, acc[d], erow + ec);
+                }
+            } else if (KIND == ACAMP) {
+                const double am = (double)m * (as_const(s.mu)[i0] - c0);
+#pragma unroll
+                for (int d = 0; d < KD; ++d) acc[d] = fma(-am, mug[min(jb + d, N - 1)] - c0, acc[d]);
+            }
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
                 const bool valid = (jb + d) <= N - 1;
