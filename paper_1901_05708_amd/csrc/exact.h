@@ -1,6 +1,7 @@
 // exact.h -- the exact FP64 distance of one pair, straight from the
 // definitions, and the helpers around it: shared by the rescoring / exact
-// search (k_finalize.hip) and the incremental profile (k_incremental.hip).
+// search (k_finalize.hip) and the incremental profile (k_incremental.hip);
+// the pipelined window walk also serves the window statistics (k_prep.hip).
 #pragma once
 
 #include "mp_internal.h"
@@ -17,9 +18,67 @@ __device__ __forceinline__ double pn_term(double d, double p)
     return pow(a, p);
 }
 
+// Calls f(a[l], b[l]) for l = 0 .. m-1 in order. Samples are loaded U at a
+// time and the loads of the next block are issued before the current block is
+// consumed, so a thread keeps 2U loads in flight instead of waiting on every
+// sample.
+template <int U, typename Fn>
+__device__ __forceinline__ void visit_pairs(gptr<double> a, gptr<double> b, int m, Fn f)
+{
+    double a0[U], b0[U], a1[U], b1[U];
+    auto load = [&](double (&x)[U], double (&y)[U], int l) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            x[u] = a[l + u];
+            y[u] = b[l + u];
+        }
+    };
+    auto run = [&](const double (&x)[U], const double (&y)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) f(x[u], y[u]);
+    };
+    const int nb = m / U;
+    if (nb > 0) load(a0, b0, 0);
+    for (int k = 0; k < nb; k += 2) {
+        if (k + 1 < nb) load(a1, b1, (k + 1) * U);
+        run(a0, b0);
+        if (k + 1 >= nb) break;
+        if (k + 2 < nb) load(a0, b0, (k + 2) * U);
+        run(a1, b1);
+    }
+    for (int l = nb * U; l < m; ++l) f(a[l], b[l]);
+}
+
+// Calls f(w[l]) for l = 0 .. m-1 in order, U samples per block, with the next
+// block's loads issued before the current block is consumed.
+template <int U, typename Fn>
+__device__ __forceinline__ void visit_window(gptr<double> w, int m, Fn f)
+{
+    double x0[U], x1[U];
+    auto load = [&](double (&x)[U], int l) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = w[l + u];
+    };
+    auto run = [&](const double (&x)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) f(x[u]);
+    };
+    const int nb = m / U;
+    if (nb > 0) load(x0, 0);
+    for (int k = 0; k < nb; k += 2) {
+        if (k + 1 < nb) load(x1, (k + 1) * U);
+        run(x0);
+        if (k + 1 >= nb) break;
+        if (k + 2 < nb) load(x0, (k + 2) * U);
+        run(x1);
+    }
+    for (int l = nb * U; l < m; ++l) f(w[l]);
+}
+
 // Exact pre-root distance of one pair, straight from Defs. 2.5-2.7:
 // sum of squares (AAMP), of p-th powers (p-norm), or DZ^2 (ACAMP, written
 // with invn = sqrt(m) / (sqrt(m) sigma) so that z = sqrt(m) (t - mu) invn).
+// Terms are summed in order of l.
 template <int KIND, int PC>
 __device__ inline double exact_sum(const Series &s, int64_t i, int64_t j)
 {
@@ -29,20 +88,21 @@ __device__ inline double exact_sum(const Series &s, int64_t i, int64_t j)
     double acc = 0.0;
     if (KIND == ACAMP) {
         const double mi = s.mu[i], mj = s.mu[j], ni = s.invn[i], nj = s.invn[j];
-        for (int l = 0; l < m; ++l) {
-            double d = (a[l] - mi) * ni - (b[l] - mj) * nj;
+        visit_pairs<8>(a, b, m, [&](double x, double y) {
+            const double d = (x - mi) * ni - (y - mj) * nj;
             acc = fma(d, d, acc);
-        }
+        });
         return acc * (double)m;
     }
     if (KIND == AAMP) {
-        for (int l = 0; l < m; ++l) {
-            double d = a[l] - b[l];
+        visit_pairs<8>(a, b, m, [&](double x, double y) {
+            const double d = x - y;
             acc = fma(d, d, acc);
-        }
+        });
         return acc;
     }
-    for (int l = 0; l < m; ++l) acc += pn_term<PC>(a[l] - b[l], s.p);
+    const double p = s.p;
+    visit_pairs<8>(a, b, m, [&](double x, double y) { acc += pn_term<PC>(x - y, p); });
     return acc;
 }
 

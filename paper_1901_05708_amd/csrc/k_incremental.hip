@@ -84,21 +84,21 @@ __global__ void k_inc_stats(IncState s, int64_t w0, int64_t w1)
     s.keys[w] = KEY_NONE;
     s.dirty[w] = 0;
     if (s.kind != ACAMP) return;
-    const double *x = s.T + w;
+    const gptr<double> x = as_global(s.T) + w;
     const int m = s.m;
     const double x0 = x[0];
     double sum = 0.0;
     bool same = true;
-    for (int l = 0; l < m; ++l) {
-        sum += x[l] - x0;
-        same = same && (x[l] == x0);
-    }
+    visit_window<8>(x, m, [&](double v) {
+        sum += v - x0;
+        same = same && (v == x0);
+    });
     const double mu = x0 + sum / (double)m;
     double ss = 0.0;
-    for (int l = 0; l < m; ++l) {
-        const double d = x[l] - mu;
+    visit_window<8>(x, m, [&](double v) {
+        const double d = v - mu;
         ss = fma(d, d, ss);
-    }
+    });
     s.mu[w] = mu;
     s.isconst[w] = same ? 1 : 0;
     s.invn[w] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
@@ -114,13 +114,14 @@ __device__ double inc_start(const IncState &s, int64_t i, int64_t j)
     double acc = 0.0;
     if (KIND == ACAMP) {
         const double mi = s.mu[i], mj = s.mu[j];
-        for (int l = 0; l < s.m; ++l) acc = fma(a[l] - mi, b[l] - mj, acc);
+        visit_pairs<8>(a, b, s.m, [&](double x, double y) { acc = fma(x - mi, y - mj, acc); });
         return acc;
     }
-    for (int l = 0; l < s.m; ++l) {
-        const double d = a[l] - b[l];
-        acc += (KIND == AAMP) ? d * d : pn_term<PC>(d, s.p);
-    }
+    const double p = s.p;
+    visit_pairs<8>(a, b, s.m, [&](double x, double y) {
+        const double d = x - y;
+        acc += (KIND == AAMP) ? d * d : pn_term<PC>(d, p);
+    });
     return acc;
 }
 

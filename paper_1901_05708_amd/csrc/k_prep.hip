@@ -1,6 +1,7 @@
 // k_prep.hip -- per-window preparation that sits outside the sweep's inner
 // loop: the O(m (n - m)) part of the method (Secs. 3.4 and 4.3), computed once
 // per window in FP64 instead of once per diagonal.
+#include "exact.h"
 #include "keys.h"
 #include "mp_internal.h"
 
@@ -18,7 +19,7 @@ __global__ void k_window_stats(Batch b)
     if (s.kind != ACAMP) return;
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= s.N) return;
-    const double *w = s.T + j;
+    const gptr<double> w = as_global(s.T) + j;
     const int m = s.m;
     // The mean is summed around the window's first sample, so its rounding
     // error scales with the window's deviations rather than with the series'
@@ -28,17 +29,16 @@ __global__ void k_window_stats(Batch b)
     double sum = 0.0;
     bool same = true;
     const double w0 = w[0];
-    for (int l = 0; l < m; ++l) {
-        double v = w[l];
+    visit_window<8>(w, m, [&](double v) {
         sum += v - w0;
         same = same && (v == w0);
-    }
+    });
     const double mu = w0 + sum / (double)m;
     double ss = 0.0;
-    for (int l = 0; l < m; ++l) {
-        double d = w[l] - mu;
+    visit_window<8>(w, m, [&](double v) {
+        const double d = v - mu;
         ss = fma(d, d, ss);
-    }
+    });
     s.mu[j] = mu;
     s.isconst[j] = same ? 1 : 0;
     s.invn[j] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
