@@ -409,9 +409,10 @@ int env_int(const char *name, int dflt)
 // and it has at least half a band of diagonals; otherwise to the simple
 // kernel (FP64 only: a single-precision request on such a job is served
 // exactly in FP64). Test hooks: MP_SWEEP=band|simple forces a kernel,
-// MP_KD=16 requests 16 diagonals per lane (FP32 only), MP_FORCE_FALLBACK=1|2
-// sends every row through the exact search, MP_COUNT_PAIRS=1 makes the sweeps
-// count the pairs they visit (reported with profiling on).
+// MP_KD=16 requests 16 diagonals per lane (FP32 only), MP_WPS=k caps the band
+// sweeps' grids at k waves per SIMD, MP_FORCE_FALLBACK=1|2 sends every row
+// through the exact search, MP_COUNT_PAIRS=1 makes the sweeps count the pairs
+// they visit (reported with profiling on).
 int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning &tu,
                 const Workspace &w, Layout *out)
 {
@@ -514,7 +515,8 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         if (!g.count || !g.rows) continue;
         const int32_t gkd = c == 1 ? kd : 8;
         int64_t slots = (int64_t)w.cus * band_blocks_per_cu(g.sels, gkd, c == 1);
-        if (tu.wps > 0) slots = std::min<int64_t>(slots, (int64_t)w.cus * 4 * tu.wps);
+        const int32_t wps = env_int("MP_WPS", 0) > 0 ? env_int("MP_WPS", 0) : tu.wps;
+        if (wps > 0) slots = std::min<int64_t>(slots, (int64_t)w.cus * 4 * wps);
         // at least 64 rows per wave
         g.grid = (int32_t)std::max<int64_t>(
             1, std::min<int64_t>(slots * std::max(1, tu.grid_mult), g.rows / 64));

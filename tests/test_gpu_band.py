@@ -193,3 +193,22 @@ def test_band_long_windows_pnorm(mp):
     T, _ = W.sines(n=7000, m=2048)
     _check(mp, "pnorm", T, 2048, p=3.0, label="long-p3")
     _check(mp, "pnorm", T, 2048, p=1.0, label="long-p1")
+
+
+@pytest.mark.parametrize("kind", ["aamp", "acamp"])
+def test_band_long_windows_long_refresh(mp, monkeypatch, kind):
+    """m = 2048 over 20000 samples with the longest refresh interval the
+    autotuner allows (16 m) and a grid of one wave per SIMD: many long items,
+    one exact restart each. Checked on sampled rows."""
+    monkeypatch.setenv("MP_WPS", "1")
+    m, R = 2048, 16 * 2048
+    T, _, _ = W.rw128k(n=20000, m=m, nruns=0, nmotifs=2, seed=31)
+    excl = W.excl_default(m)
+    N = len(T) - m + 1
+    rows = W.sample_rows(N, 192, 32)
+    _note(f"long-refresh {kind}: n={len(T)} m={m} R={R} wps=1")
+    P, I = _call(mp, kind, T, m, excl=excl, R=R)
+    Pr, Ir, Qr = oracle.profile(T, m, kind, excl=excl, rows=rows)
+    atol = 1e-6 if kind == "acamp" else 0.0
+    check_profile(T, m, kind, 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, 1e-9, atol, rows=rows,
+                  label=f"long-refresh-{kind}")

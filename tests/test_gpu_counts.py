@@ -104,3 +104,20 @@ def test_batch_visits_every_pair_once(mp, monkeypatch, prec):
     visited, pairs = _visits(mp, lambda: mp.batch(T_cat, jobs, precision=prec))
     assert pairs == expect
     assert visited == expect
+
+
+@pytest.mark.parametrize("wps", [1, 2])
+def test_capped_grids_visit_every_pair_once(mp, monkeypatch, wps):
+    """Grids capped at one or two waves per SIMD (the long-window autotuner
+    candidates) and refresh intervals of 16 m still split the band rows
+    exactly."""
+    import torch
+    monkeypatch.setenv("MP_COUNT_PAIRS", "1")
+    monkeypatch.setenv("MP_WPS", str(wps))
+    for n, m, R in ((131072, 256, 4096), (60000, 2048, 32768)):
+        T = torch.as_tensor(np.cumsum(np.random.default_rng(n + wps).standard_normal(n)), device="cuda")
+        print(f"[gpu-case] counts wps={wps} n={n} m={m} R={R}", flush=True)
+        for kind in ("aamp", "acamp"):
+            fn = (lambda: mp.aamp(T, m, R=R)) if kind == "aamp" else (lambda: mp.acamp(T, m, R=R))
+            visited, pairs = _visits(mp, fn)
+            assert visited == pairs == mp.pair_count(n, m, W.excl_default(m))
