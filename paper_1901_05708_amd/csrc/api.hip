@@ -356,6 +356,18 @@ int32_t default_R(uint32_t sel, bool fp32, int32_t m)
     }
 }
 
+// Where a band's exact restart goes in the split of the row space: a band of
+// L rows takes band_cost + L positions, so that a wave whose share holds many
+// short bands (the end of every triangle) is not left with all their
+// restarts. The restart costs about m FMAs per diagonal against about 8 VALU
+// operations per pair and row in the sweep (Euclidean, z-normalized; the
+// p-norm restarts take 2-4 operations per sample).
+int32_t band_cost(uint32_t sel, int32_t m)
+{
+    const bool pnorm = sel == SEL_P1 || sel == SEL_P3;
+    return pnorm ? (m + 3) / 4 : (m + 7) / 8;
+}
+
 // Rows summed over all bands (band b: N - excl - b W rows) and the band count.
 int64_t band_rows_total(int64_t N, int64_t excl, int64_t W, int64_t *nbands)
 {
@@ -430,7 +442,8 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
     L.count = env_int("MP_COUNT_PAIRS", 0) == 1;
 
     std::vector<Job> cls[3];          // FP64 band, FP32 band, other
-    std::vector<int64_t> rows_of[3];
+    std::vector<int64_t> rows_of[3];  // band rows
+    std::vector<int64_t> pos_of[3];   // positions in the row space (rows + restart costs)
     for (const Spec &sp : specs) {
         Job j;
         std::memset(&j, 0, sizeof(j));
@@ -459,6 +472,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         int64_t rows = 0, nb = 0;
         if (band) {
             rows = band_rows_total(s.N, s.excl, W, &nb);
+            j.band_cost = band_cost(sel, s.m);
             int64_t R = sp.R > 0 ? sp.R
                                  : (tu.R > 0 && s.fp32 == want32 ? tu.R : default_R(sel, s.fp32, s.m));
             j.seg_rows = (int32_t)std::min<int64_t>(R, INT32_MAX / 2);
@@ -478,6 +492,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         const int c = band ? (s.fp32 ? 1 : 0) : 2;
         cls[c].push_back(j);
         rows_of[c].push_back(rows);
+        pos_of[c].push_back(rows + nb * (int64_t)j.band_cost);
     }
     for (int c = 0; c < 3; ++c) {
         if (c < 2) {
@@ -486,13 +501,14 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
             g.count = (int32_t)cls[c].size();
             g.rb_off = (int64_t)L.row_base.size();
         }
-        int64_t run = 0;
+        int64_t run = 0, real = 0;
         for (size_t k = 0; k < cls[c].size(); ++k) {
             Job j = cls[c][k];
             const Series &s = j.s;
             j.row_start = run;
             if (c < 2) L.row_base.push_back(run);
-            run += rows_of[c][k];
+            run += pos_of[c][k];
+            real += rows_of[c][k];
             j.band_base = L.band_entries;
             L.band_entries += j.nbands + 1;
             j.key_base = L.key_total;
@@ -506,7 +522,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         }
         if (c < 2) {
             L.row_base.push_back(run);
-            L.g[c].rows = run;
+            L.g[c].rows = real;
         }
     }
     L.kd = kd;

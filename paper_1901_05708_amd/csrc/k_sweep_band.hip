@@ -655,10 +655,11 @@ __global__ void __launch_bounds__(64)
     cint64 *band_start = as_const(b.band_start);
     const int64_t total = row_base[b.njobs];   // band-row positions of the launch
 
-    // This wave's share of the band-row space: every row of a band costs the
-    // same (pairs past the series end run on sentinels), so equal row ranges
-    // are nearly equal work. share = total / G rows, the first total % G waves
-    // take one more.
+    // This wave's share of the row space: every row of a band costs the same
+    // (pairs past the series end run on sentinels), and each band is preceded
+    // by band_cost positions that stand for its exact restart, so equal
+    // position ranges are nearly equal work. share = total / G positions, the
+    // first total % G waves take one more.
     const int64_t G = gridDim.x;
     const int64_t w = blockIdx.x;
     const int64_t qrows = total / G, rrows = total % G;
@@ -686,40 +687,49 @@ __global__ void __launch_bounds__(64)
             else hi = mid;
         }
         lo = __builtin_amdgcn_readfirstlane(lo);
-        // one item: rows of band lo from pos up to the end of the share, the
-        // band, or the refresh interval, whichever comes first
+        // band lo holds positions [bs[lo], bs[lo + 1]): band_cost positions for
+        // its restart, then one per row. One item: the rows of band lo from pos
+        // up to the end of the share, the band, or the refresh interval,
+        // whichever comes first; a share that ends among the restart positions
+        // holds no row of the band.
         const int64_t k_lo = uniform64((int64_t)s.excl + (int64_t)lo * RING);
-        const int64_t seg = uniform64(min(min(pend, bs[lo + 1]), pos + (int64_t)J.seg_rows) - pos);
-        const int64_t i0 = uniform64(pos - bs[lo]);
-        pos += seg;
+        const int64_t row0 = uniform64(bs[lo] + J.band_cost);   // position of row 0
+        const int64_t i0 = uniform64(max(pos - row0, (int64_t)0));
+        const int64_t lim = uniform64(min(pend, bs[lo + 1]) - row0);
+        const int64_t i1 = uniform64(min(lim, i0 + (int64_t)J.seg_rows));
+        if (i1 <= i0) {
+            pos = min(pend, bs[lo + 1]);
+            continue;
+        }
+        pos = row0 + i1;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
-            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
+            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
-            band_item<ACAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
+            band_item<ACAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_P1) && sel == SEL_P1)
-            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
+            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
-            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i0 + seg, ring, rowbuf, stage, b.visits);
+            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
     }
 }
 
 // Band table of every job (one block per job): bs[t] = row_base of the job +
-// rows of its bands before t, where band t has N - excl - t W rows; the last
-// entry bs[nbands] is the job's end.
+// positions of its bands before t, where band t has N - excl - t W rows and
+// takes band_cost more positions; the last entry bs[nbands] is the job's end.
 __global__ void __launch_bounds__(1024) k_band_plan(Batch b)
 {
     __shared__ int64_t part[1024];
     const Job J = load_uniform(&b.jobs[blockIdx.x]);
     const int64_t base = J.row_start;
-    const int64_t N = J.s.N, excl = J.s.excl, W = b.band_width;
+    const int64_t N = J.s.N, excl = J.s.excl, W = b.band_width, C = J.band_cost;
     const int nb = J.nbands;
     int64_t *bs = b.band_start + J.band_base;
     const int t = threadIdx.x;
     const int per = (nb + 1023) / 1024;
     const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
     int64_t sum = 0;
-    for (int u = b0; u < b1; ++u) sum += N - excl - (int64_t)u * W;
+    for (int u = b0; u < b1; ++u) sum += C + N - excl - (int64_t)u * W;
     part[t] = sum;
     __syncthreads();
     if (t == 0) {
@@ -735,7 +745,7 @@ __global__ void __launch_bounds__(1024) k_band_plan(Batch b)
     int64_t run = part[t];
     for (int u = b0; u < b1; ++u) {
         bs[u] = run;
-        run += N - excl - (int64_t)u * W;
+        run += C + N - excl - (int64_t)u * W;
     }
 }
 

@@ -105,11 +105,13 @@ struct Job {
     Series s;              // views of the job's slices of the workspace
     double *P;             // N outputs
     int64_t *I;
-    int64_t row_start;     // first band-row position of the job in its sweep's row space
+    int64_t row_start;     // first position of the job in its sweep's row space
     int64_t band_base;     // first entry of the job's band table
     int64_t key_base;      // offset of the job's windows in the launch's key space
     int32_t nbands;        // bands of the band kernel (0: simple kernel, or no pairs)
     int32_t seg_rows;      // rows between exact restarts (refresh interval R)
+    int32_t band_cost;     // positions a band takes in the row space before its rows
+    int32_t pad1;
 };
 
 // Every array the kernels touch lives in device global memory. Addressing it
