@@ -286,8 +286,8 @@ def incremental(mp, h, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); every GPU box here has "
-              "one GPU and this build has no multi-GPU path.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1901_05708_amd as mp

@@ -27,7 +27,7 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
-    # no packed FP32 instructions anywhere (build notes)
+    # no packed FP32 instructions in any HIP code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(HERE, "..", "include"),
 ]
