@@ -336,19 +336,20 @@ struct Tuning {
 // Longest FP64 refresh interval per window length. A step's rounding error is
 // relative to the per-sample scale of the streams (offset, low-variance
 // windows are the hard case), while the quantity it perturbs grows with m, so
-// the drift after R steps falls with m at a fixed R / m. 16 is the ratio of
-// R = 4096 at m = 256; with window means summed around each window's first
-// sample, affine copies with offset / scale = 1e6 showed no drift beyond the
-// 1e-9 bound up to R / m = 256, so the cap leaves a wide margin.
-constexpr int64_t FP64_R_PER_M = 16;
+// the drift after R steps falls with m at a fixed R / m. With window means
+// summed around each window's first sample, random walks with constant runs
+// and planted motifs, and their affine copies with offset / scale = 1e6,
+// showed no drift beyond the 1e-9 bound up to R / m = 256 (m = 256, 1024,
+// 4096); the cap of 64 leaves a factor 4.
+constexpr int64_t FP64_R_PER_M = 64;
 
 // Default refresh intervals. In FP64, 4096, or 16 m for long windows: R only
-// trades the restart cost (2m per diagonal) against item count. In FP32 every
+// trades the restart cost (m per diagonal) against item count. In FP32 every
 // step can add 2^-24 relative error; the values below minimise sweep plus
 // exact-search time on the series shapes measured.
 int32_t default_R(uint32_t sel, bool fp32, int32_t m)
 {
-    if (!fp32) return (int32_t)std::min<int64_t>(std::max<int64_t>(4096, FP64_R_PER_M * m), 1 << 24);
+    if (!fp32) return (int32_t)std::min<int64_t>(std::max<int64_t>(4096, 16 * (int64_t)m), 1 << 24);
     switch (sel) {
     case SEL_ACAMP: return 512;
     case SEL_P1: return 1024;
