@@ -1,7 +1,6 @@
 // exact.h -- the exact FP64 distance of one pair, straight from the
 // definitions, and the helpers around it: shared by the rescoring / exact
-// search (k_finalize.hip) and the incremental profile (k_incremental.hip);
-// the pipelined window walk also serves the window statistics (k_prep.hip).
+// search (k_finalize.hip) and the incremental profile (k_incremental.hip).
 #pragma once
 
 #include "mp_internal.h"
@@ -75,6 +74,23 @@ __device__ __forceinline__ void visit_window(gptr<double> w, int m, Fn f)
     for (int l = nb * U; l < m; ++l) f(w[l]);
 }
 
+// One term of the exact sums: the squared difference of the z-normalized
+// samples (times 1/m), the squared difference, or |difference|^p.
+template <int KIND, int PC>
+__device__ __forceinline__ double exact_term(double x, double y, double mi, double ni, double mj,
+                                             double nj, double p, double acc)
+{
+    if (KIND == ACAMP) {
+        const double d = (x - mi) * ni - (y - mj) * nj;
+        return fma(d, d, acc);
+    }
+    if (KIND == AAMP) {
+        const double d = x - y;
+        return fma(d, d, acc);
+    }
+    return acc + pn_term<PC>(x - y, p);
+}
+
 // Exact pre-root distance of one pair, straight from Defs. 2.5-2.7:
 // sum of squares (AAMP), of p-th powers (p-norm), or DZ^2 (ACAMP, written
 // with invn = sqrt(m) / (sqrt(m) sigma) so that z = sqrt(m) (t - mu) invn).
@@ -86,24 +102,18 @@ __device__ inline double exact_sum(const Series &s, int64_t i, int64_t j)
     const gptr<double> b = as_global(s.T) + j;
     const int m = s.m;
     double acc = 0.0;
-    if (KIND == ACAMP) {
-        const double mi = s.mu[i], mj = s.mu[j], ni = s.invn[i], nj = s.invn[j];
-        visit_pairs<8>(a, b, m, [&](double x, double y) {
-            const double d = (x - mi) * ni - (y - mj) * nj;
-            acc = fma(d, d, acc);
-        });
-        return acc * (double)m;
-    }
-    if (KIND == AAMP) {
-        visit_pairs<8>(a, b, m, [&](double x, double y) {
-            const double d = x - y;
-            acc = fma(d, d, acc);
-        });
-        return acc;
-    }
     const double p = s.p;
-    visit_pairs<8>(a, b, m, [&](double x, double y) { acc += pn_term<PC>(x - y, p); });
-    return acc;
+    double mi = 0.0, mj = 0.0, ni = 0.0, nj = 0.0;
+    if (KIND == ACAMP) {
+        mi = s.mu[i];
+        mj = s.mu[j];
+        ni = s.invn[i];
+        nj = s.invn[j];
+    }
+    visit_pairs<8>(a, b, m, [&](double x, double y) {
+        acc = exact_term<KIND, PC>(x, y, mi, ni, mj, nj, p, acc);
+    });
+    return (KIND == ACAMP) ? acc * (double)m : acc;
 }
 
 template <int KIND, int PC>

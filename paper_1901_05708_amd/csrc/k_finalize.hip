@@ -27,23 +27,36 @@ __device__ __forceinline__ void enqueue(const Fallback &fb, int32_t jb, int64_t 
     fb.job_flag[jb] = 1;
 }
 
-template <int KIND, int PC>
-__device__ __forceinline__ void finalize_row(const Series &s, const Fallback &fb, int32_t jb,
-                                             int64_t i, double *P, int64_t *I)
+// First part of a row's finalize: rows without a candidate get +inf / -1,
+// rows whose winner is not a legal candidate go to the exact search; returns
+// true (with the winner j) when the winner's exact distance is needed.
+template <int KIND>
+__device__ __forceinline__ bool finalize_decode(const Series &s, const Fallback &fb, int32_t jb,
+                                                int64_t i, double *P, int64_t *I, int64_t *j_out)
 {
     const unsigned long long mask = (1ull << s.gb) - 1ull;
     const unsigned long long key = s.keys[i];
     if ((KIND == ACAMP && s.isconst[i]) || key == KEY_NONE) {
         P[i] = __longlong_as_double(0x7FF0000000000000ll);
         I[i] = -1;
-        return;
+        return false;
     }
     const int64_t j = (int64_t)(key & mask);
     if (!legal_pair(s, i, j)) {
         enqueue(fb, jb, i, KEY_NONE, __longlong_as_double(0x7FF0000000000000ll));
-        return;
+        return false;
     }
-    const double ex = exact_sum<KIND, PC>(s, i, j);
+    *j_out = j;
+    return true;
+}
+
+// Second part, given the exact pre-root distance ex of (i, j).
+template <int KIND, int PC>
+__device__ __forceinline__ void finalize_finish(const Series &s, const Fallback &fb, int32_t jb,
+                                                int64_t i, int64_t j, double ex, double *P,
+                                                int64_t *I)
+{
+    const unsigned long long mask = (1ull << s.gb) - 1ull;
     if (s.force_fb) {
         if (s.force_fb == 1)
             enqueue(fb, jb, i, pack_key(ex, (unsigned long long)j, mask), root_of<KIND, PC>(ex, s.p));
@@ -58,7 +71,7 @@ __device__ __forceinline__ void finalize_row(const Series &s, const Fallback &fb
         // again exactly, starting from this winner. The key holds the
         // minimised quantity: the sum (AAMP, p-norm) or 1 - rho = DZ^2 / 2m
         // (ACAMP).
-        const double kv = key_value(key, mask);
+        const double kv = key_value(s.keys[i], mask);
         const double xv = (KIND == ACAMP) ? ex / (2.0 * (double)s.m) : ex;
         const double pscale = (KIND == PNORM) ? 0.5 * s.p : 1.0;
         const double tol = FP32_SELF_CHECK * pscale * fabs(xv) +
@@ -73,19 +86,122 @@ __device__ __forceinline__ void finalize_row(const Series &s, const Fallback &fb
     I[i] = j;
 }
 
-// Grid: x over windows, y over jobs.
-__global__ void k_finalize(Batch b)
+constexpr int FIN_BLOCK = 256;   // rows per block of k_finalize
+constexpr int FIN_CHUNK = 64;    // steps per staged chunk
+
+// LDS of a k_finalize block: the staged row and winner samples and the
+// block's range of winner diagonals.
+struct FinLds {
+    double sa[FIN_BLOCK + FIN_CHUNK];
+    double sb[FIN_BLOCK + FIN_CHUNK];
+    long long dlo, dhi;
+    int any;
+};
+
+// Rows i0 .. i0 + 255 of one job, one thread each. At step l the rows need
+// the samples t[i0 + l .. i0 + l + 255], one contiguous run, which is staged
+// in LDS chunk by chunk (the next chunk's loads issued before the current one
+// is consumed). When every winner of the block lies on one diagonal
+// (j = i + d, the common case: neighbouring windows' best matches shift
+// together), the winners' samples are a contiguous run too and are staged the
+// same way; otherwise each thread loads its winner's samples. Every exact sum
+// adds its terms in order of l, with the same terms as exact_sum.
+template <int KIND, int PC>
+__device__ __forceinline__ void finalize_block(const Series &s, const Fallback &fb, int32_t jb,
+                                               int64_t i0, double *P, int64_t *I, FinLds &L)
+{
+    constexpr int B = FIN_BLOCK, CH = FIN_CHUNK, SPAN = B + CH;
+    double *sa = L.sa, *sb = L.sb;
+    const int t = threadIdx.x;
+    const int64_t i = i0 + t;
+    int64_t j = 0;
+    const bool need = i < s.N && finalize_decode<KIND>(s, fb, jb, i, P, I, &j);
+    if (t == 0) {
+        L.dlo = INT64_MAX;
+        L.dhi = INT64_MIN;
+        L.any = 0;
+    }
+    __syncthreads();
+    if (need) {
+        atomicMin(&L.dlo, (long long)(j - i));
+        atomicMax(&L.dhi, (long long)(j - i));
+        L.any = 1;
+    }
+    __syncthreads();
+    if (!L.any) return;   // block-uniform
+    const bool diag = L.dlo == L.dhi;
+    const int64_t d = L.dlo;
+    const gptr<double> T = as_global(s.T);
+    const int64_t tmax = s.n - 1;
+    const int m = s.m;
+    const double p = s.p;
+    double mi = 0.0, mj = 0.0, ni = 0.0, nj = 0.0;
+    if (KIND == ACAMP && need) {
+        mi = s.mu[i];
+        mj = s.mu[j];
+        ni = s.invn[i];
+        nj = s.invn[j];
+    }
+    double ra0, ra1, rb0 = 0.0, rb1 = 0.0;
+    auto fetch = [&](int l0) {
+        ra0 = T[min(i0 + l0 + t, tmax)];
+        ra1 = (t + B < SPAN) ? T[min(i0 + l0 + t + B, tmax)] : 0.0;
+        if (diag) {
+            // rows that need no sum stage samples too; the diagonal may put
+            // their positions before the series start, so clamp both ends
+            rb0 = T[min(max(i0 + d + l0 + t, (int64_t)0), tmax)];
+            rb1 = (t + B < SPAN) ? T[min(max(i0 + d + l0 + t + B, (int64_t)0), tmax)] : 0.0;
+        }
+    };
+    auto put = [&]() {
+        __syncthreads();
+        sa[t] = ra0;
+        if (t + B < SPAN) sa[t + B] = ra1;
+        if (diag) {
+            sb[t] = rb0;
+            if (t + B < SPAN) sb[t + B] = rb1;
+        }
+        __syncthreads();
+    };
+    // a winner's own samples, when the block has no common diagonal
+    // (rows that need no sum read t[0], which always exists)
+    const gptr<double> tb = T + (need ? j : 0);
+    double acc = 0.0;
+    fetch(0);
+    put();
+    for (int l0 = 0; l0 < m; l0 += CH) {
+        const bool more = l0 + CH < m;
+        if (more) fetch(l0 + CH);
+        const int steps = min(CH, m - l0);
+        if (diag) {
+            for (int u = 0; u < steps; ++u)
+                acc = exact_term<KIND, PC>(sa[t + u], sb[t + u], mi, ni, mj, nj, p, acc);
+        } else if (need) {
+            for (int u = 0; u < steps; ++u)
+                acc = exact_term<KIND, PC>(sa[t + u], tb[l0 + u], mi, ni, mj, nj, p, acc);
+        }
+        if (more) put();
+    }
+    if (need) {
+        const double ex = (KIND == ACAMP) ? acc * (double)m : acc;
+        finalize_finish<KIND, PC>(s, fb, jb, i, j, ex, P, I);
+    }
+}
+
+// Grid: x over blocks of FIN_BLOCK windows, y over jobs.
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Batch b)
 {
     const int32_t jb = blockIdx.y;
     const Job J = load_uniform(&b.jobs[jb]);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= J.s.N) return;
+    const int64_t i0 = (int64_t)blockIdx.x * FIN_BLOCK;
+    if (i0 >= J.s.N) return;   // block-uniform
+    __shared__ FinLds L;
     switch (sel_of(J.s.kind, J.s.pclass)) {
-    case SEL_AAMP: finalize_row<AAMP, P_TWO>(J.s, b.fb, jb, i, J.P, J.I); break;
-    case SEL_ACAMP: finalize_row<ACAMP, P_TWO>(J.s, b.fb, jb, i, J.P, J.I); break;
-    case SEL_P1: finalize_row<PNORM, P_ONE>(J.s, b.fb, jb, i, J.P, J.I); break;
-    case SEL_P3: finalize_row<PNORM, P_THREE>(J.s, b.fb, jb, i, J.P, J.I); break;
-    default: finalize_row<PNORM, P_GENERIC>(J.s, b.fb, jb, i, J.P, J.I); break;
+    case SEL_AAMP: finalize_block<AAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
+    case SEL_ACAMP: finalize_block<ACAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
+    case SEL_P1: finalize_block<PNORM, P_ONE>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
+    case SEL_P3: finalize_block<PNORM, P_THREE>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
+    default: finalize_block<PNORM, P_GENERIC>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
     }
 }
 
@@ -338,9 +454,8 @@ __global__ void k_fallback_finish(Batch b)
 hipError_t launch_finalize(const Batch &b, hipStream_t st)
 {
     if (b.njobs <= 0) return hipSuccess;
-    const int B = 256;
-    dim3 g((unsigned)((b.max_N + B - 1) / B), (unsigned)b.njobs);
-    hipLaunchKernelGGL(k_finalize, g, dim3(B), 0, st, b);
+    dim3 g((unsigned)((b.max_N + FIN_BLOCK - 1) / FIN_BLOCK), (unsigned)b.njobs);
+    hipLaunchKernelGGL(k_finalize, g, dim3(FIN_BLOCK), 0, st, b);
     return hipGetLastError();
 }
 

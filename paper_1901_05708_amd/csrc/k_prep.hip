@@ -1,7 +1,6 @@
 // k_prep.hip -- per-window preparation that sits outside the sweep's inner
 // loop: the O(m (n - m)) part of the method (Secs. 3.4 and 4.3), computed once
 // per window in FP64 instead of once per diagonal.
-#include "exact.h"
 #include "keys.h"
 #include "mp_internal.h"
 
@@ -13,14 +12,56 @@ namespace mpk {
 // window (no running sums, so no cancellation over long series). A constant
 // window gets invn = 0; its z-normalized distance to anything is infinite
 // (Sec. 1) and the sweep never lets it win.
-__global__ void k_window_stats(Batch b)
+constexpr int STATS_BLOCK = 256;   // windows per block of k_window_stats
+constexpr int STATS_CHUNK = 64;    // steps per staged chunk
+
+__global__ void __launch_bounds__(STATS_BLOCK) k_window_stats(Batch b)
 {
     const Series s = load_uniform(&b.jobs[blockIdx.y]).s;
     if (s.kind != ACAMP) return;
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= s.N) return;
-    const gptr<double> w = as_global(s.T) + j;
+    // The block's windows j0 .. j0 + 255 need, at step l, the samples
+    // t[j0 + l .. j0 + l + 255]: one contiguous run. Chunks of STATS_CHUNK
+    // steps are staged in LDS (the next chunk's loads are issued before the
+    // current one is consumed) and each thread reads its window's sample of
+    // the step from there, instead of a global load per window and sample.
+    constexpr int B = STATS_BLOCK, CH = STATS_CHUNK, SPAN = B + CH;
+    __shared__ double st[SPAN];
+    const int t = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * B;
+    if (j0 >= s.N) return;
+    const int64_t j = j0 + t;
+    const gptr<double> T = as_global(s.T);
+    const int64_t tmax = s.n - 1;
     const int m = s.m;
+    double r0, r1;
+    auto fetch = [&](int l0) {
+        r0 = T[min(j0 + l0 + t, tmax)];
+        r1 = (t + B < SPAN) ? T[min(j0 + l0 + t + B, tmax)] : 0.0;
+    };
+    auto put = [&]() {
+        __syncthreads();
+        st[t] = r0;
+        if (t + B < SPAN) st[t + B] = r1;
+        __syncthreads();
+    };
+    // f(t[j + l]) for l = 0 .. m-1 in order (every thread of the block takes
+    // part, also those past the last window, for the barriers)
+    auto walk = [&](auto &&f) {
+        fetch(0);
+        put();
+        for (int l0 = 0; l0 < m; l0 += CH) {
+            const bool more = l0 + CH < m;
+            if (more) fetch(l0 + CH);
+            const int steps = min(CH, m - l0);
+            if (steps == CH) {
+#pragma unroll 16
+                for (int u = 0; u < CH; ++u) f(st[t + u]);
+            } else {
+                for (int u = 0; u < steps; ++u) f(st[t + u]);
+            }
+            if (more) put();
+        }
+    };
     // The mean is summed around the window's first sample, so its rounding
     // error scales with the window's deviations rather than with the series'
     // offset. Neighbouring windows share all but one sample, so a plain sum's
@@ -28,20 +69,22 @@ __global__ void k_window_stats(Batch b)
     // covariance recurrence would accumulate them as drift.
     double sum = 0.0;
     bool same = true;
-    const double w0 = w[0];
-    visit_window<8>(w, m, [&](double v) {
+    const double w0 = T[min(j, tmax)];
+    walk([&](double v) {
         sum += v - w0;
         same = same && (v == w0);
     });
     const double mu = w0 + sum / (double)m;
     double ss = 0.0;
-    visit_window<8>(w, m, [&](double v) {
+    walk([&](double v) {
         const double d = v - mu;
         ss = fma(d, d, ss);
     });
-    s.mu[j] = mu;
-    s.isconst[j] = same ? 1 : 0;
-    s.invn[j] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
+    if (j < s.N) {
+        s.mu[j] = mu;
+        s.isconst[j] = same ? 1 : 0;
+        s.invn[j] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
+    }
 }
 
 // Per-window difference streams used by the O(1) diagonal updates, and the
@@ -160,8 +203,8 @@ hipError_t launch_prep(const Batch &b, uint32_t sels, hipStream_t st)
     const int B = 256;
     if (b.njobs <= 0) return hipSuccess;
     if (sels & SEL_ACAMP) {
-        dim3 g((unsigned)((b.max_N + B - 1) / B), (unsigned)b.njobs);
-        hipLaunchKernelGGL(k_window_stats, g, dim3(B), 0, st, b);
+        dim3 g((unsigned)((b.max_N + STATS_BLOCK - 1) / STATS_BLOCK), (unsigned)b.njobs);
+        hipLaunchKernelGGL(k_window_stats, g, dim3(STATS_BLOCK), 0, st, b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
