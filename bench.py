@@ -114,16 +114,17 @@ def cpu_model():
     return "unknown"
 
 
-def sweep_traffic():
-    """HBM bytes per launch of the FP64 ACAMP sweep from the committed
-    rocprofv3 counter summary, or None when the kernel source changed since
-    the counters were taken."""
+def sweep_traffic(refresh_rows):
+    """HBM bytes per launch of the FP64 ACAMP sweep at this refresh interval,
+    from the committed rocprofv3 counter summary; None when the summary has
+    no entry for it or the kernel source changed since the counters were
+    taken."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
     want = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
-    got = re.search(r"traffic_bytes_per_launch:\s*([0-9]+)", text)
+    got = re.search(r"traffic_bytes_per_launch\[R=%d\]:\s*([0-9]+)" % int(refresh_rows), text)
     if not want or not got:
         return None
     have = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
@@ -332,7 +333,7 @@ def main():
             "peak": round(peak, 3),
             "unit": "Tlane-ops/s",
             "frac": round(achieved / peak, 4),
-            "traffic": sweep_traffic(),
+            "traffic": sweep_traffic(f64["refresh_rows"]),
             "ops_per_pair": OPS_PER_PAIR["acamp"],
             "kernel_ms": round(f64["sweep_ms"], 4),
         },
