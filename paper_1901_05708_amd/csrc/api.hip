@@ -362,9 +362,11 @@ int32_t default_R(uint32_t sel, bool fp32, int32_t m)
 // short bands (the end of every triangle) is not left with all their
 // restarts. The restart costs about m FMAs per diagonal against about 8 VALU
 // operations per pair and row in the sweep (Euclidean, z-normalized; the
-// p-norm restarts take 2-4 operations per sample).
+// p-norm restarts take 2-4 operations per sample, and for other p one pow
+// per sample against two per pair).
 int32_t band_cost(uint32_t sel, int32_t m)
 {
+    if (sel == SEL_PGEN) return (m + 1) / 2;
     const bool pnorm = sel == SEL_P1 || sel == SEL_P3;
     return pnorm ? (m + 3) / 4 : (m + 7) / 8;
 }
@@ -442,6 +444,11 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
     if (force_fb != 1 && force_fb != 2) force_fb = 0;
     L.count = env_int("MP_COUNT_PAIRS", 0) == 1;
 
+    // p-norms with other p than 1, 2, 3 get a band kernel only in a launch
+    // of such jobs alone (their kernel holds no other distance)
+    bool all_pgen = true;
+    for (const Spec &sp : specs)
+        all_pgen = all_pgen && sel_of(sp.kind, sp.pclass) == SEL_PGEN && sp.p <= PGEN_BAND_MAX;
     std::vector<Job> cls[3];          // FP64 band, FP32 band, other
     std::vector<int64_t> rows_of[3];  // band rows
     std::vector<int64_t> pos_of[3];   // positions in the row space (rows + restart costs)
@@ -466,8 +473,9 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         // the sweep this job would join decides its band width
         const bool single = want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
         const int64_t W = 64 * (single ? kd : 8);
-        bool band = (sel & SEL_BAND) && ndiag >= W / 2 && choice != "simple";
-        if (choice == "band" && (sel & SEL_BAND) && ndiag > 0) band = true;
+        const bool has_band = (sel & SEL_BAND) || (sel == SEL_PGEN && all_pgen);
+        bool band = has_band && ndiag >= W / 2 && choice != "simple";
+        if (choice == "band" && has_band && ndiag > 0) band = true;
         if (ndiag <= 0) band = false;
         s.fp32 = (single && band) ? 1 : 0;
         int64_t rows = 0, nb = 0;

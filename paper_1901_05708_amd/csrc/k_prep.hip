@@ -125,7 +125,7 @@ __global__ void k_streams(Batch b)
             x = SENT_EUCLID;
             y = SENT_EUCLID;
         } else if (s.kind == PNORM) {
-            x = (s.pclass == P_ONE) ? SENT_P1 : (s.pclass == P_THREE ? SENT_P3 : 0.0);
+            x = (s.pclass == P_ONE) ? SENT_P1 : (s.pclass == P_THREE ? SENT_P3 : sent_pgen(s.p));
             y = 0.0;
         }
     } else if (j >= 1) {

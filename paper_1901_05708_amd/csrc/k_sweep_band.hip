@@ -174,11 +174,12 @@ struct Prec<float> {
 };
 
 template <int PC, typename F>
-__device__ __forceinline__ F pw(F d)
+__device__ __forceinline__ F pw(F d, double p)
 {
     F a = fabs(d);
     if (PC == P_ONE) return a;
-    return a * a * a;  // P_THREE
+    if (PC == P_THREE) return a * a * a;
+    return (F)pow((double)a, p);   // P_GENERIC (FP64 sweeps only)
 }
 
 // A workgroup is a single wavefront and LDS executes one wave's accesses in
@@ -333,7 +334,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                     for (int d = 0; d < KD; ++d) e[d] = tr - win[(q + d) % KD];
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int d = 0; d < KD; ++d) acc[d] += pw<PC, double>(e[d]);
+                    for (int d = 0; d < KD; ++d) acc[d] += pw<PC, double>(e[d], s.p);
                 }
             };
             for (int l0 = 0; l0 < m; l0 += LCH) {
@@ -570,7 +571,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                         S[d] = fma(rx - cx[sl], ry - cy[sl], S[d]);
                         v[d] = S[d];
                     } else if (KIND == PNORM) {
-                        S[d] += pw<PC, F>(rx - cx[sl]) - pw<PC, F>(ry - cy[sl]);
+                        S[d] += pw<PC, F>(rx - cx[sl], s.p) - pw<PC, F>(ry - cy[sl], s.p);
                         v[d] = S[d];
                     } else {
                         S[d] = fma(rx, cy[sl], S[d]);
@@ -711,6 +712,8 @@ __global__ void __launch_bounds__(64)
             band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
             band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
+        else if ((SELS & SEL_PGEN) && sel == SEL_PGEN)
+            band_item<PNORM, P_GENERIC, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
     }
 }
 
@@ -759,11 +762,16 @@ hipError_t launch_plan(const Batch &b, hipStream_t st)
 namespace {
 
 // Kernel of a selector set: one of its own for a single specialisation,
-// otherwise the mixed kernel holding all band specialisations. The
-// pair-counting test mode always uses the mixed kernel.
+// otherwise the mixed kernel holding the specialisations of SEL_BAND. The
+// pair-counting test mode uses the mixed kernel, or for generic p its own.
 template <int KD, typename F>
 const void *band_kernel(uint32_t sels, bool count)
 {
+    if constexpr (sizeof(F) == 8) {
+        if (sels == SEL_PGEN)
+            return count ? (const void *)k_sweep_band<SEL_PGEN, KD, F, true>
+                         : (const void *)k_sweep_band<SEL_PGEN, KD, F, false>;
+    }
     if (count) return (const void *)k_sweep_band<SEL_BAND, KD, F, true>;
     switch (sels & SEL_BAND) {
     case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP, KD, F, false>;
@@ -786,7 +794,7 @@ const void *band_kernel_for(uint32_t sels, int32_t kd, bool fp32, bool count)
 hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_lane, bool fp32,
                              int32_t grid, hipStream_t st)
 {
-    if (grid <= 0 || !(sels & SEL_BAND)) return hipSuccess;
+    if (grid <= 0 || !(sels & (SEL_BAND | SEL_PGEN))) return hipSuccess;
     const void *k = band_kernel_for(sels, diags_per_lane, fp32, b.visits != nullptr);
     Batch arg = b;
     void *args[] = {&arg};

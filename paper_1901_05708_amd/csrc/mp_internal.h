@@ -27,6 +27,8 @@ constexpr double SENT_EUCLID = -1e100;   // u = v = -1e100: each step adds ~1e20
 constexpr double SENT_P1 = -1e200;       // |a_i - a_j| ~ 1e200
 constexpr double SENT_P3 = -1e66;        // |a_i - a_j|^3 ~ 1e198
 constexpr double SENT_INIT = 1e200;      // start value of a diagonal already past N
+// generic p (1 < p <= 6): -(1e30 + 10^(198/p)), so |a_i - a_j|^p ~ 1e198
+__host__ __device__ inline double sent_pgen(double p) { return -(1e30 + pow(10.0, 198.0 / p)); }
 // float-stream sentinels (the sums of pairs touching them exceed 1e30 or are +inf)
 constexpr float SENTF_EUCLID = -1e18f;
 constexpr float SENTF_P1 = -1e30f;
@@ -186,9 +188,15 @@ __host__ __device__ inline uint32_t sel_of(int32_t kind, int32_t pclass)
     return SEL_PGEN;
 }
 
-// Band kernels exist for AAMP, ACAMP and p-norm with p in {1, 3}; other p use
-// the simple kernel (the sentinel entries are only sized for those powers).
+// Band kernels exist for AAMP, ACAMP and p-norm with p in {1, 3} (one kernel
+// may hold any mix of them), and for other p up to PGEN_BAND_MAX in kernels
+// of their own: a launch whose jobs are all such p-norms. Other p use the
+// simple kernel.
 constexpr uint32_t SEL_BAND = SEL_AAMP | SEL_ACAMP | SEL_P1 | SEL_P3;
+// With |t| < 1e30 a term |a - b|^p stays below (2e30)^6 = 6.4e181 for p <= 6,
+// so no real sum reaches the 1e190 of the sentinel sums and nothing in the
+// recurrence overflows.
+constexpr double PGEN_BAND_MAX = 6.0;
 
 // --- launch wrappers (return the hipError_t of the launch) -------------------
 // The row_base table of a one-job launch (at most 3 entries: the two band

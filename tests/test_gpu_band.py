@@ -212,3 +212,29 @@ def test_band_long_windows_long_refresh(mp, monkeypatch, kind):
     atol = 1e-6 if kind == "acamp" else 0.0
     check_profile(T, m, kind, 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, 1e-9, atol, rows=rows,
                   label=f"long-refresh-{kind}")
+
+
+# ---- p-norms with other p (1 < p <= 6): a band kernel of their own ----
+
+@pytest.mark.parametrize("p", [1.5, 2.5, 4.7, 6.0])
+def test_band_generic_p(mp, p):
+    """pow per term in the sweep and the restarts; sentinels sized per p."""
+    rng = np.random.default_rng(1300 + int(10 * p))
+    T = np.cumsum(rng.standard_normal(3000))
+    _check(mp, "pnorm", T, 32, p=p, label=f"pgen-{p}")
+
+
+def test_band_generic_p_long_and_offset(mp):
+    T, _ = W.sines(n=7000, m=512)
+    _check(mp, "pnorm", T + 500.0, 512, p=2.5, label="pgen-long-offset")
+
+
+def test_generic_p_above_band_limit_uses_simple_kernel(mp):
+    """p = 7 would let real terms approach the sentinel sums; it stays on the
+    simple kernel and must still match the oracle."""
+    rng = np.random.default_rng(1377)
+    T = np.cumsum(rng.standard_normal(1500))
+    excl = W.excl_default(24)
+    P, I = _call(mp, "pnorm", T, 24, p=7.0, excl=excl, sweep="auto")
+    Pr, Ir, Qr = oracle.profile(T, 24, "pnorm", p=7.0, excl=excl)
+    check_profile(T, 24, "pnorm", 7.0, excl, P, I, Pr, Ir, Qr, 1e-9, 0.0, label="pgen-7")

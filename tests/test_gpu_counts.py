@@ -41,7 +41,9 @@ CASES = [
     ("acamp", 2.0, 4000, 64, 1, 100, "fp32", "auto"),
     ("pnorm", 1.0, 3000, 32, 0, 0, "fp32", "auto"),
     ("pnorm", 3.0, 3000, 32, 0, 0, "fp64", "auto"),
-    ("pnorm", 1.5, 1200, 16, 0, 0, "fp64", "auto"),       # generic p: simple kernel
+    ("pnorm", 1.5, 1200, 16, 0, 0, "fp64", "auto"),       # generic p: its own band kernel
+    ("pnorm", 2.5, 5000, 48, 0, 37, "fp64", "auto"),      # generic p, short segments
+    ("pnorm", 7.0, 1200, 16, 0, 0, "fp64", "auto"),       # p > 6: simple kernel
     ("aamp", 2.0, 300, 16, 0, 0, "fp64", "auto"),         # below half a band: simple
     ("acamp", 2.0, 300, 16, 0, 0, "fp64", "band"),        # forced band, one partial band
     ("aamp", 2.0, 40, 40, 0, 0, "fp64", "auto"),          # one window, no pairs
