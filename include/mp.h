@@ -91,7 +91,10 @@ int mp_aamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precisi
  * mp_pnorm -- p-norm matrix profile (AAMP extended to L^p, Sec. 3.3).
  * Distance: DP_{i,j} = (sum_{l<m} |t_{i+l} - t_{j+l}|^p)^(1/p)  (Def. 2.6, Eq. 2,
  * read with an absolute value), real p >= 1; updated with Lemma 2. p = 2 gives
- * exactly the result of mp_aamp. p must be finite and >= 1.
+ * exactly the result of mp_aamp. p must be finite and >= 1. p = 1 and 3 have
+ * fast paths; other p up to 6 evaluate pow per term in the band sweep (FP64,
+ * also under MP_FP32_REFRESH); larger p, and other p inside a batch holding
+ * other distances, run on a slower one-thread-per-diagonal sweep.
  */
 int mp_pnorm(const double *T, int64_t n, int32_t m, double p, int32_t excl,
              int32_t precision, int32_t R, double *P, int64_t *I, void *stream);
