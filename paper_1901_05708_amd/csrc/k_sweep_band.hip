@@ -7,13 +7,15 @@
 //
 //  * A work item is a band of 64*KD consecutive diagonals [k_lo, k_lo + 64 KD)
 //    times a run of rows [i0, i1). One wavefront owns one item at a time; each
-//    wave of the persistent grid owns an equal share of the band-major rows.
+//    wave of the persistent grid owns an equal share of the band-major rows,
+//    where every band also counts the cost of its restart.
 //  * Lane l owns the KD diagonals k_lo + KD l + d. All 64 lanes step through
 //    the rows together, so the row operands are wave-uniform (scalar loads) and
 //    the column operands of a step are KD-strided in the column stream.
-//  * Each item starts with the exact FP64 sums of its first row (the refresh),
-//    then runs the O(1) recurrence for the remaining rows, in the precision F:
-//    double, or float with the start values rounded from the FP64 sums.
+//  * Each item starts with FP64 sums of its first row taken over the m samples
+//    of each window pair (the refresh), then runs the O(1) recurrence for the
+//    remaining rows, in the precision F: double, or float with the start
+//    values rounded from the FP64 sums.
 //  * Column operands come from an LDS ring: the stream entries of the item's
 //    columns are staged once (coalesced, one block of KD entries per KD steps,
 //    fetched a block ahead) and each step every lane reads the one entry that
@@ -623,11 +625,12 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
     }
 }
 
-// Resident waves per SIMD the compiler is asked for. The FP64 AAMP and
-// p-norm kernels fit 3 waves (168 VGPRs) at the cost of a few spills outside
-// the inner loop, 2-4 % faster than 2 waves; the FP64 ACAMP and mixed kernels
-// would spill inside it (ACAMP: 55 % slower) and keep the default. FP32 with 8
-// diagonals per lane fits 4 waves without spills.
+// Resident waves per SIMD the compiler is asked for. The FP64 AAMP and p = 1,
+// 3 kernels fit 3 waves (168 VGPRs) at the cost of a few spills outside the
+// inner loop, 2-4 % faster than 2 waves. The FP64 ACAMP kernel holds three
+// ring fields (16 KB of LDS per wave), so 12 waves do not fit a CU's 160 KB;
+// asking for 3 was 55 % slower. It, the mixed and the generic-p kernels keep
+// the default. FP32 with 8 diagonals per lane fits 4 waves without spills.
 template <uint32_t SELS, int KD, typename F>
 constexpr int waves_target()
 {
