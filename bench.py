@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
+    ap.add_argument("--configs", action="store_true",
+                    help="also time the other single-series workloads (rw8k, sines p = 1 and 3, "
+                         "ecg ACAMP and AAMP) in both precisions; adds a minute or two")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 + refresh runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: auto)")
@@ -193,6 +196,55 @@ def headline(args, mp, W, torch):
             "P": out["PI"][0].cpu().numpy(),
             "I": out["PI"][1].cpu().numpy(),
         }
+    return res
+
+
+def other_configs(args, mp, W, torch):
+    """The other single-series workloads, each autotuned and then timed over a
+    few calls in FP64 and FP32 + refresh: pairs/s end to end, the FP32 gain and
+    the exact-search rows. Returns a dict keyed by workload."""
+    runs = []
+    T, m = W.rw8k()
+    runs.append(("rw8k_aamp", T, m, "aamp", 2.0, 20))
+    T, m = W.sines()
+    runs.append(("sines_p1", T, m, "pnorm", 1.0, 5))
+    runs.append(("sines_p3", T, m, "pnorm", 3.0, 5))
+    T, m, _ = W.ecg()
+    runs.append(("ecg_acamp", T, m, "acamp", 2.0, 2))
+    runs.append(("ecg_aamp", T, m, "aamp", 2.0, 2))
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, T, m, kind, p, steps in runs:
+        Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
+        excl = W.excl_default(m)
+        pairs = mp.pair_count(len(T), m, excl)
+        row = {"n": len(T), "m": m, "p": p, "pairs": pairs}
+        for prec in ("fp64", "fp32"):
+            def step():
+                if kind == "aamp":
+                    mp.aamp(Td, m, excl=excl, precision=prec, stream=stream, validate=False)
+                elif kind == "acamp":
+                    mp.acamp(Td, m, excl=excl, precision=prec, stream=stream, validate=False)
+                else:
+                    mp.pnorm(Td, m, p=p, excl=excl, precision=prec, stream=stream, validate=False)
+            print(f"[configs] {name} {prec}: autotune and timing", file=sys.stderr, flush=True)
+            mp.set_profiling(False)
+            step()                          # autotuner
+            torch.cuda.synchronize()
+            mp.set_profiling(True)
+            ms, _ = timed(step, steps, 1, stream)
+            prof = mp.profile_read()
+            mp.set_profiling(False)
+            calls = max(1, prof["calls"])
+            row[prec] = {"ms_per_step": round(ms, 3),
+                         "value": round(pairs / (ms * 1e-3) / 1e9, 1),
+                         "refresh_rows": prof["refresh_rows"],
+                         "diags_per_lane": prof["diags_per_lane"],
+                         "fallback_rows_per_step": round(prof["fallback_rows"] / calls, 1)}
+        row["fp32_gain"] = round(row["fp32"]["value"] / row["fp64"]["value"], 3)
+        res[name] = row
+        print(f"[configs] {name}: fp64 {row['fp64']['value']} fp32 {row['fp32']['value']} Gpairs/s",
+              file=sys.stderr, flush=True)
     return res
 
 
@@ -378,6 +430,8 @@ def main():
     out["incremental"] = incremental(mp, h, torch)
     if not args.no_batch:
         out["batch"] = batch_workload(args, mp, W, torch)
+    if args.configs:
+        out["configs"] = other_configs(args, mp, W, torch)
     if args.copy_calib > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
         # calibrate the ones read for the sweep
