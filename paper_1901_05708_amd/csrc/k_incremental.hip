@@ -14,7 +14,8 @@
 //  * k_inc_columns: one thread per diagonal walks the chunk's new columns,
 //    starting from the stored last column or, at a refresh and on diagonals
 //    that begin inside the chunk, from an exact FP64 sum; rows whose packed
-//    key improves are flagged.
+//    key improves are flagged. All threads take the same column at a step,
+//    so its key is reduced over the wave before its one atomic.
 //  * k_inc_rescore: flagged rows and the new windows take their exact FP64
 //    distance (as the one-shot path does).
 // A first load, and any append longer than a fraction of the series, runs the
@@ -31,6 +32,9 @@
 #include "mp_internal.h"
 
 namespace mpk {
+
+constexpr int INC_BLOCK = 256;        // threads per block of the column walk
+constexpr int64_t INC_COLS = 2048;    // new columns per column launch at most
 
 // Device views of an incremental state; N is the number of windows after the
 // chunk being processed.
@@ -140,38 +144,75 @@ __device__ __forceinline__ double inc_step(const IncState &s, int64_t i, int64_t
     return fma(dfi, dgj, dfj * dgi);
 }
 
-// Diagonal k = excl + thread, over the chunk's new columns [w0, w1].
-template <int KIND, int PC>
-__global__ void __launch_bounds__(256) k_inc_columns(IncState s, int64_t w0, int64_t w1,
-                                                     int32_t refresh)
+// Smallest key over the 64 lanes of the wave (every lane takes part).
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
 {
-    const int64_t k = (int64_t)s.excl + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > w1) return;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long y = __shfl_xor(x, off, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// Diagonal k = excl + thread, over the chunk's new columns [w0, w1]. All
+// threads step through the columns together (column j = w0 + t at step t); a
+// diagonal joins at its first new column with a row (j = max(k, w0)). Each
+// pair updates its row's key with its own atomic. The column's key is the
+// same for the whole grid at a step: it takes the minimum over the wave, then
+// over the block in LDS, and the block adds one global atomic per column at
+// the end.
+template <int KIND, int PC>
+__global__ void __launch_bounds__(INC_BLOCK) k_inc_columns(IncState s, int64_t w0, int64_t w1,
+                                                           int32_t refresh)
+{
+    __shared__ unsigned long long colk[INC_COLS];
+    const int64_t steps = w1 - w0 + 1;           // <= INC_COLS, checked by the host
+    for (int64_t t = threadIdx.x; t < steps; t += INC_BLOCK) colk[t] = KEY_NONE;
+
+    const int64_t k = (int64_t)s.excl + (int64_t)blockIdx.x * INC_BLOCK + threadIdx.x;
+    const bool mine = k <= w1;                    // a diagonal of the chunk
     const unsigned long long mask = (1ull << s.gb) - 1ull;
     const int64_t js = k > w0 ? k : w0;          // first new column with row >= 0
-    int64_t i = js - k;
-    double S;
-    if (!refresh && js == w0 && i >= 1)
-        S = s.col_old[i - 1] + inc_step<KIND, PC>(s, i, js);
-    else
-        S = inc_start<KIND, PC>(s, i, js);
-    for (int64_t j = js;; ++j, ++i) {
-        if (j > js) S += inc_step<KIND, PC>(s, i, j);
-        bool ok = true;
-        double v = S;
-        if (KIND == ACAMP) {
-            ok = !s.isconst[i] && !s.isconst[j];
-            v = fma(S * s.invn[i], -s.invn[j], 1.0);     // 1 - rho
-        }
-        if (ok) {
-            const unsigned long long ki = pack_key(v, (unsigned long long)j, mask);
-            const unsigned long long old = atomicMin(&s.keys[i], ki);
-            if (ki < old && i < w0) s.dirty[i] = 1;
-            atomicMin(&s.keys[j], pack_key(v, (unsigned long long)i, mask));
-        }
-        if (j == w1) break;
+    // The start of every diagonal, taken before the walk so that the lanes
+    // of a wave compute theirs together.
+    double S = 0.0;
+    if (mine) {
+        const int64_t i = js - k;
+        if (!refresh && js == w0 && i >= 1)
+            S = s.col_old[i - 1] + inc_step<KIND, PC>(s, i, js);
+        else
+            S = inc_start<KIND, PC>(s, i, js);
     }
-    s.col_new[w1 - k] = S;
+    __syncthreads();
+    for (int64_t t = 0; t < steps; ++t) {
+        const int64_t j = w0 + t;
+        const int64_t i = j - k;
+        unsigned long long kc = KEY_NONE;
+        if (mine && j >= js) {
+            if (j > js) S += inc_step<KIND, PC>(s, i, j);
+            bool ok = true;
+            double v = S;
+            if (KIND == ACAMP) {
+                ok = !s.isconst[i] && !s.isconst[j];
+                v = fma(S * s.invn[i], -s.invn[j], 1.0);     // 1 - rho
+            }
+            if (ok) {
+                const unsigned long long ki = pack_key(v, (unsigned long long)j, mask);
+                const unsigned long long old = atomicMin(&s.keys[i], ki);
+                if (ki < old && i < w0) s.dirty[i] = 1;
+                kc = pack_key(v, (unsigned long long)i, mask);
+            }
+        }
+        kc = wave_min_u64(kc);
+        if ((threadIdx.x & 63) == 0 && kc != KEY_NONE) atomicMin(&colk[t], kc);
+    }
+    if (mine) s.col_new[w1 - k] = S;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < steps; t += INC_BLOCK) {
+        const unsigned long long kc = colk[t];
+        if (kc != KEY_NONE) atomicMin(&s.keys[w0 + t], kc);
+    }
 }
 
 // Rows [0, w1]: flagged old rows and every new window take the exact FP64
@@ -228,8 +269,10 @@ static hipError_t launch_chunk(const IncState &s, int64_t w0, int64_t w1, bool r
     hipLaunchKernelGGL(k_inc_stats, dim3((unsigned)((w1 - w0 + B) / B)), dim3(B), 0, st, s, w0, w1);
     if (w1 >= s.excl) {
         const int64_t nd = w1 - s.excl + 1;
-        hipLaunchKernelGGL((k_inc_columns<KIND, PC>), dim3((unsigned)((nd + B - 1) / B)), dim3(B),
-                           0, st, s, w0, w1, (int32_t)(refresh ? 1 : 0));
+        if (w1 - w0 + 1 > INC_COLS) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_inc_columns<KIND, PC>),
+                           dim3((unsigned)((nd + INC_BLOCK - 1) / INC_BLOCK)), dim3(INC_BLOCK), 0,
+                           st, s, w0, w1, (int32_t)(refresh ? 1 : 0));
     }
     hipLaunchKernelGGL((k_inc_rescore<KIND, PC>), dim3((unsigned)((w1 + B) / B)), dim3(B), 0, st,
                        s, w0, w1);
@@ -270,8 +313,6 @@ struct mp_inc {
 };
 
 namespace {
-
-constexpr int64_t INC_CHUNK = 2048;     // windows per column launch
 
 int32_t inc_index_bits(int64_t N)
 {
@@ -400,7 +441,7 @@ int mp_inc_append(mp_inc *h, const double *T, int64_t count, void *stream)
     const int64_t N_old = n_old >= h->m ? n_old - h->m + 1 : 0;
     const int64_t N_new = n_new - h->m + 1;
     const int64_t added = N_new - N_old;
-    if (N_old == 0 || added > std::max<int64_t>(INC_CHUNK, N_old / 8)) {
+    if (N_old == 0 || added > std::max<int64_t>(INC_COLS, N_old / 8)) {
         // one-shot profile of the whole series, then rebuild the state
         int rc = profile_once(h->T, n_new, h->m, h->kind, h->p, h->excl, 4096, h->P, h->I, st);
         if (rc) return rc;
@@ -418,7 +459,7 @@ int mp_inc_append(mp_inc *h, const double *T, int64_t count, void *stream)
     while (w0 < N_new) {
         const bool restart = h->since_refresh == 0;
         const int64_t len = std::min<int64_t>(
-            {N_new - w0, INC_CHUNK, (int64_t)h->refresh - h->since_refresh});
+            {N_new - w0, INC_COLS, (int64_t)h->refresh - h->since_refresh});
         const int64_t w1 = w0 + len - 1;
         const IncState s = view(h, w1 + 1);
         e = dispatch(h->kind, h->pclass, [&](auto K, auto PC) {

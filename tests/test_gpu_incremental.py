@@ -128,3 +128,35 @@ def test_pnorm_two_equals_aamp(mp):
     Pb, Ib = b.profile()
     assert np.array_equal(Pa.cpu().numpy(), Pb.cpu().numpy())
     assert np.array_equal(Ia.cpu().numpy(), Ib.cpu().numpy())
+
+
+@pytest.mark.parametrize("kind", ["aamp", "acamp"])
+def test_widest_column_launches(mp, kind):
+    """Appends of 2048 and 2049 windows to 20000: the first fills one column
+    launch (2048 new columns, the most one launch takes), the second runs
+    2048 more up to the restart and one after it. All new windows and a
+    sample of old rows are checked against the oracle."""
+    import torch
+    rng = np.random.default_rng(17)
+    m = 16
+    n0 = 20000 + m - 1
+    full = np.cumsum(rng.standard_normal(n0 + 2048 + 2049))
+    if kind == "acamp":
+        full[n0 + 700:n0 + 760] = full[n0 + 700]     # a constant run inside the launch
+    excl = W.excl_default(m)
+    inc = mp.Incremental(m, kind=kind, capacity=len(full), refresh=4096)
+    inc.append(torch.as_tensor(full[:n0], device="cuda"))          # one-shot path
+    for lo, hi in ((n0, n0 + 2048), (n0 + 2048, len(full))):
+        inc.append(torch.as_tensor(full[lo:hi], device="cuda"))
+        _note(f"widest column launch {kind} n={hi}")
+        T = full[:hi]
+        N = hi - m + 1
+        rows = np.unique(np.concatenate([rng.choice(20000, size=600, replace=False),
+                                         np.arange(20000, N)]))
+        P, I = inc.profile()
+        P = P.cpu().numpy()[rows]
+        I = I.cpu().numpy()[rows]
+        Pr, Ir, Qr = oracle.profile(T, m, kind, excl=excl, rows=rows)
+        check_profile(T, m, kind, 2.0, excl, P, I, Pr, Ir, Qr, 1e-9,
+                      1e-6 if kind == "acamp" else 0.0, rows=rows, label=f"inc-wide-{kind}-n{hi}")
+    inc.close()
