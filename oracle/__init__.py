@@ -46,6 +46,10 @@ def _bind(lib):
                                    ctypes.c_double, ctypes.c_int32, lp, ctypes.c_int64,
                                    dp, lp, dp, ctypes.c_int32]
     lib.oracle_profile.restype = ctypes.c_int
+    lib.oracle_profile_diagonals.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_double, ctypes.c_int32, u8p, lp,
+                                             ctypes.c_int64, dp, lp, dp, ctypes.c_int32]
+    lib.oracle_profile_diagonals.restype = ctypes.c_int
     lib.oracle_window_stats.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, dp, dp, u8p]
     lib.oracle_window_stats.restype = ctypes.c_int
     lib.oracle_distance.argtypes = [dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -78,9 +82,13 @@ def _kind(kind) -> int:
 
 
 def profile(T, m: int, kind="aamp", p: float = 2.0, excl: int = 1, rows=None,
-            nthreads: int = 0):
+            nthreads: int = 0, diagonals=None):
     """Matrix profile by brute force. Returns (P, I, Q) as numpy arrays,
-    one entry per row in ``rows`` (all N rows when rows is None)."""
+    one entry per row in ``rows`` (all N rows when rows is None).
+
+    ``diagonals``: optional boolean mask of N entries; only pairs whose
+    diagonal |i - j| is marked are candidates (the profile an anytime sweep
+    has after visiting exactly those diagonals)."""
     T = np.ascontiguousarray(T, dtype=np.float64)
     n = T.shape[0]
     N = n - m + 1
@@ -93,9 +101,18 @@ def profile(T, m: int, kind="aamp", p: float = 2.0, excl: int = 1, rows=None,
     P = np.empty(max(R, 0), dtype=np.float64)
     I = np.empty(max(R, 0), dtype=np.int64)
     Q = np.empty(max(R, 0), dtype=np.float64)
-    rc = _load().oracle_profile(_dptr(T), n, m, _kind(kind), float(p), int(excl),
-                                _lptr(rows_arr) if rows_arr is not None else None, R,
-                                _dptr(P), _lptr(I), _dptr(Q), int(nthreads))
+    rows_p = _lptr(rows_arr) if rows_arr is not None else None
+    if diagonals is None:
+        rc = _load().oracle_profile(_dptr(T), n, m, _kind(kind), float(p), int(excl), rows_p, R,
+                                    _dptr(P), _lptr(I), _dptr(Q), int(nthreads))
+    else:
+        mask = np.ascontiguousarray(diagonals, dtype=np.uint8)
+        if mask.shape != (max(N, 0),):
+            raise ValueError("diagonals must hold one entry per window")
+        rc = _load().oracle_profile_diagonals(
+            _dptr(T), n, m, _kind(kind), float(p), int(excl),
+            mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), rows_p, R,
+            _dptr(P), _lptr(I), _dptr(Q), int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle_profile rejected its arguments (rc={rc})")
     return P, I, Q

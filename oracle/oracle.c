@@ -31,6 +31,13 @@
  *   runner-up     Q_i = the best distance over admissible j != I_i.
  *
  * Rows with no finite candidate get P = +inf, I = -1, Q = +inf.
+ *
+ * Partial profiles (oracle_profile_diagonals): the same minimum taken only
+ * over the pairs whose diagonal k = |i - j| is marked in a mask. Each outer
+ * iteration k of the paper's algorithms (Sec. 3.2, Algs. 1-3) visits exactly
+ * the pairs of diagonal k and nothing carries from one k to the next, which
+ * is why the paper can call the algorithms anytime (Sec. 1, Sec. 7): stopping
+ * after any set of iterations leaves the profile over those diagonals.
  */
 #include <math.h>
 #include <stdint.h>
@@ -155,9 +162,33 @@ double oracle_distance(const double *T, int64_t n, int32_t m, int32_t kind,
  * position in the row list. Q may be NULL. nthreads <= 0 uses the OpenMP
  * default. Returns 0, or -1 on invalid arguments.
  */
+static int profile_impl(const double *T, int64_t n, int32_t m, int32_t kind,
+                        double p, int32_t excl, const uint8_t *diag_ok,
+                        const int64_t *rows, int64_t nrows,
+                        double *P, int64_t *I, double *Q, int32_t nthreads);
+
 int oracle_profile(const double *T, int64_t n, int32_t m, int32_t kind,
                    double p, int32_t excl, const int64_t *rows, int64_t nrows,
                    double *P, int64_t *I, double *Q, int32_t nthreads)
+{
+    return profile_impl(T, n, m, kind, p, excl, NULL, rows, nrows, P, I, Q, nthreads);
+}
+
+/* diag_ok: N entries; pair (i, j) is a candidate only if diag_ok[|i - j|] is
+ * nonzero (and |i - j| >= excl as before). */
+int oracle_profile_diagonals(const double *T, int64_t n, int32_t m, int32_t kind,
+                             double p, int32_t excl, const uint8_t *diag_ok,
+                             const int64_t *rows, int64_t nrows,
+                             double *P, int64_t *I, double *Q, int32_t nthreads)
+{
+    if (!diag_ok) return -1;
+    return profile_impl(T, n, m, kind, p, excl, diag_ok, rows, nrows, P, I, Q, nthreads);
+}
+
+static int profile_impl(const double *T, int64_t n, int32_t m, int32_t kind,
+                        double p, int32_t excl, const uint8_t *diag_ok,
+                        const int64_t *rows, int64_t nrows,
+                        double *P, int64_t *I, double *Q, int32_t nthreads)
 {
     if (!T || !P || !I || n < 1 || m < 1 || m > n || excl < 1) return -1;
     if (kind < ORACLE_EUCLID || kind > ORACLE_ZNORM) return -1;
@@ -194,6 +225,7 @@ int oracle_profile(const double *T, int64_t n, int32_t m, int32_t kind,
         for (int64_t j = 0; row_ok && j < N; ++j) {
             int64_t gap = i > j ? i - j : j - i;
             if (gap < excl) continue;
+            if (diag_ok && !diag_ok[gap]) continue;
             if (kind == ORACLE_ZNORM && isconst[j]) continue;
             double s = pair_sum(T, m, kind, p, ip, i, j, mu, sigma);
             if (s < best) {

@@ -29,6 +29,8 @@ MUTANTS = {
     "pnorm_no_abs": ("double a = fabs(x);", "double a = x;"),
     "wrong_mean": ("double mean = T[i] + s / (double)m;", "double mean = T[i] + s / (double)(m + 1);"),
     "root_dropped": ("        if (p == 2.0) return sqrt(s);\n", "        if (p == 2.0) return s;\n"),
+    "mask_ignored": ("            if (diag_ok && !diag_ok[gap]) continue;\n", ""),
+    "mask_off_by_one": ("!diag_ok[gap]", "!diag_ok[gap - 1]"),
 }
 
 PIN_TESTS = [
@@ -40,6 +42,7 @@ PIN_TESTS = [
     lambda o: pins.test_exact_integer_euclid_pnorm(o, 2),
     lambda o: pins.test_exact_rational_znorm(o),
     lambda o: pins.test_constant_series(o),
+    lambda o: pins.test_diagonal_mask_matches_library(o),
 ]
 
 

@@ -121,6 +121,64 @@ def _check_against(P, I, Q, Pr, Ir, Qr, rtol):
     assert np.array_equal(I[sep], Ir[sep])
 
 
+def test_diagonal_mask_matches_library(oracle_mod):
+    """Partial profiles (the anytime reading of Sec. 1 / Sec. 7: stopping
+    after a set of outer iterations k leaves the minimum over exactly those
+    diagonals): the oracle's masked profile equals the row minimum of a
+    library pairwise matrix with the unmarked diagonals removed."""
+    rng = np.random.default_rng(12)
+    T = np.cumsum(rng.standard_normal(300))
+    m, excl = 16, 4
+    W = sliding_window_view(T, m)
+    N = W.shape[0]
+    mask = rng.random(N) < 0.3
+    idx = np.arange(N)
+    off = ~mask[np.abs(idx[:, None] - idx[None, :])]
+
+    def lib(S, root):
+        S = S.copy()
+        S[off] = np.inf
+        return _lib_profile(S, excl, root)
+
+    P, I, Q = oracle_mod.profile(T, m, "aamp", excl=excl, diagonals=mask)
+    _check_against(P, I, Q, *lib(cdist(W, W, "sqeuclidean"), np.sqrt), 1e-11)
+    P, I, Q = oracle_mod.profile(T, m, "pnorm", p=3.0, excl=excl, diagonals=mask)
+    _check_against(P, I, Q, *lib(cdist(W, W, "minkowski", p=3.0), lambda x: x), 1e-10)
+    P, I, Q = oracle_mod.profile(T, m, "acamp", excl=excl, diagonals=mask)
+    r = np.corrcoef(W)
+    _check_against(P, I, Q, *lib(2.0 * m * (1.0 - r), lambda x: np.sqrt(np.maximum(x, 0))),
+                   1e-8)
+
+
+def test_diagonal_mask_union_and_extremes(oracle_mod):
+    rng = np.random.default_rng(13)
+    T = np.cumsum(rng.standard_normal(260))
+    m, excl = 12, 3
+    N = len(T) - m + 1
+    full = oracle_mod.profile(T, m, "acamp", excl=excl)
+    every = oracle_mod.profile(T, m, "acamp", excl=excl, diagonals=np.ones(N, bool))
+    for a, b in zip(full, every):
+        assert np.array_equal(a, b)
+    P0, I0, _ = oracle_mod.profile(T, m, "aamp", excl=excl, diagonals=np.zeros(N, bool))
+    assert np.all(np.isinf(P0)) and np.all(I0 == -1)
+    # one diagonal k: the partner of row i is i - k or i + k
+    k = 37
+    one = np.zeros(N, bool)
+    one[k] = True
+    P1, I1, _ = oracle_mod.profile(T, m, "aamp", excl=excl, diagonals=one)
+    i = np.arange(N)
+    assert np.all((I1 == i - k) | (I1 == i + k))
+    for r in (0, 5, N - 1, N // 2):
+        assert P1[r] == pytest.approx(np.linalg.norm(T[r:r + m] - T[I1[r]:I1[r] + m]), rel=1e-12)
+    # the union of two masks takes the smaller of the two profiles
+    A = rng.random(N) < 0.2
+    B = rng.random(N) < 0.2
+    PA, _, _ = oracle_mod.profile(T, m, "aamp", excl=excl, diagonals=A)
+    PB, _, _ = oracle_mod.profile(T, m, "aamp", excl=excl, diagonals=B)
+    PU, _, _ = oracle_mod.profile(T, m, "aamp", excl=excl, diagonals=A | B)
+    assert np.array_equal(PU, np.minimum(PA, PB))
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_scipy_cdist_euclid_and_pnorm(oracle_mod, seed):
     rng = np.random.default_rng(seed)
