@@ -153,6 +153,54 @@ int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pre
              double *P_cat, int64_t *I_cat, void *stream);
 
 /*
+ * Partial (anytime) sweeps. Every outer iteration k of Algorithms 1-3 visits
+ * the pairs of diagonal k only, and nothing carries from one iteration to the
+ * next; the paper calls the algorithms anytime for this reason (Sec. 1,
+ * Sec. 7). A sweep stopped after any set of diagonals leaves, for every row,
+ * the exact distance to the best partner on those diagonals: an upper bound on
+ * the row's profile value that only decreases as more diagonals are visited,
+ * and equal to it once all are.
+ *
+ * The diagonals excl .. N-1 (N = n - m + 1) are cut into groups of
+ * MP_ANYTIME_GROUP: group g holds diagonals [excl + g*512, excl + (g+1)*512)
+ * that are below N, so there are ceil((N - excl) / 512) groups (0 when
+ * N <= excl). Work per group is proportional to its pairs, about 512 (N - d).
+ *
+ * mp_anytime_groups: *ngroups receives the number of groups of (n, m, excl);
+ *   excl <= 0 means ceil(m/4). Host only.
+ * mp_anytime_order: writes a uniformly random permutation of the groups to
+ *   the HOST array order (mp_anytime_groups entries), drawn by Fisher-Yates
+ *   with splitmix64 from seed (STAMP-style random order, Sec. 6), and, if
+ *   cum_pairs is not null, the number of admissible pairs covered after each
+ *   prefix of it (HOST int64 array of the same size; the last entry is the
+ *   total pair count). Host only; never touches the GPU.
+ * mp_anytime: the profile over the diagonals of the listed groups. T, P, I
+ *   and the distance arguments are as for mp_aamp / mp_pnorm / mp_acamp
+ *   (device pointers, FP64 precision, R chosen by the library); kind is
+ *   MP_KIND_*; p-norms need p <= 6. groups is a HOST array of ngroups group
+ *   indices in [0, mp_anytime_groups) (read during the call only; repeats
+ *   cost work but do not change the result); ngroups = 0 visits nothing.
+ *   resume = 0: P, I receive the profile over those diagonals (+inf / -1 for
+ *     rows without a candidate there).
+ *   resume = 1: P, I must hold on entry the output of an earlier mp_anytime
+ *     or full-profile call on the same series and arguments; every row keeps
+ *     the better of its entry and the new candidates (equal distances: the
+ *     smaller index), so a sequence of calls over groups A, B, ... gives the
+ *     profile over their union.
+ *   Rows are rescored exactly in FP64 as in the full profile; P[i] is the
+ *   distance of (i, I[i]). Errors: MP_EINVAL for a bad group index, ngroups
+ *   < 0, resume not 0 or 1, p > 6, or the single-series argument errors.
+ *   Stream-ordered and asynchronous; uses the device workspace.
+ */
+#define MP_ANYTIME_GROUP 512
+int mp_anytime_groups(int64_t n, int32_t m, int32_t excl, int64_t *ngroups);
+int mp_anytime_order(int64_t n, int32_t m, int32_t excl, uint64_t seed, int32_t *order,
+                     int64_t *cum_pairs);
+int mp_anytime(int32_t kind, const double *T, int64_t n, int32_t m, double p, int32_t excl,
+               const int32_t *groups, int64_t ngroups, int32_t resume, double *P, int64_t *I,
+               void *stream);
+
+/*
  * mp_topk -- motifs or discords of a computed profile, the two uses of the
  * matrix profile named in Sec. 1. P and I are the N outputs of one mp_aamp /
  * mp_pnorm / mp_acamp call (device pointers).

@@ -27,9 +27,11 @@ MP_FP64, MP_FP32_REFRESH = 0, 1
 KIND_AAMP, KIND_PNORM, KIND_ACAMP = 0, 1, 2
 FP32_RTOL = 1e-4
 
-EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_topk", "mp_inc_create",
-            "mp_inc_append", "mp_inc_state", "mp_inc_read", "mp_inc_destroy", "mp_strerror",
-            "mp_release", "mp_set_profiling", "mp_profile_read")
+EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_topk", "mp_anytime",
+            "mp_anytime_groups", "mp_anytime_order", "mp_inc_create", "mp_inc_append",
+            "mp_inc_state", "mp_inc_read", "mp_inc_destroy", "mp_strerror", "mp_release",
+            "mp_set_profiling", "mp_profile_read")
+ANYTIME_GROUP = 512
 MP_MOTIFS, MP_DISCORDS = 0, 1
 
 
@@ -78,6 +80,12 @@ def load(path: str = LIB_PATH):
     for f in (lib.mp_aamp, lib.mp_pnorm, lib.mp_acamp, lib.mp_batch):
         f.restype = ctypes.c_int
     lib.mp_topk.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.mp_anytime.argtypes = [i32, vp, i64, i32, dbl, i32, vp, i64, i32, vp, vp, vp]
+    lib.mp_anytime.restype = ctypes.c_int
+    lib.mp_anytime_groups.argtypes = [i64, i32, i32, ctypes.POINTER(i64)]
+    lib.mp_anytime_groups.restype = ctypes.c_int
+    lib.mp_anytime_order.argtypes = [i64, i32, i32, ctypes.c_uint64, vp, vp]
+    lib.mp_anytime_order.restype = ctypes.c_int
     lib.mp_topk.restype = ctypes.c_int
     lib.mp_inc_create.argtypes = [i32, i32, dbl, i32, i64, i32, ctypes.POINTER(vp)]
     lib.mp_inc_create.restype = ctypes.c_int
@@ -247,6 +255,104 @@ def topk(P, I, k: int, excl: int, mode: str = "motifs", stream=None):
                           oj.data_ptr(), od.data_ptr(), cnt.data_ptr(), _stream(stream)))
     c = int(cnt.item())
     return oi[:c], oj[:c], od[:c]
+
+
+_KIND_OF = {"aamp": KIND_AAMP, "pnorm": KIND_PNORM, "acamp": KIND_ACAMP}
+
+
+def anytime_groups(n: int, m: int, excl: Optional[int] = None) -> int:
+    """Number of diagonal groups (ANYTIME_GROUP diagonals each) of a series
+    (mp_anytime_groups; host only)."""
+    G = ctypes.c_int64()
+    _check(load().mp_anytime_groups(int(n), int(m), int(excl or 0), ctypes.byref(G)))
+    return G.value
+
+
+def anytime_order(n: int, m: int, excl: Optional[int] = None, seed: int = 0):
+    """Seeded random order of the diagonal groups and the admissible pairs
+    covered after each prefix of it (mp_anytime_order; host only). Returns
+    (order int32, cum_pairs int64) numpy arrays."""
+    import numpy as np
+    G = anytime_groups(n, m, excl)
+    order = np.empty(G, dtype=np.int32)
+    cum = np.empty(G, dtype=np.int64)
+    _check(load().mp_anytime_order(int(n), int(m), int(excl or 0),
+                                   ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                   order.ctypes.data_as(ctypes.c_void_p),
+                                   cum.ctypes.data_as(ctypes.c_void_p)))
+    return order, cum
+
+
+def anytime(T, m: int, groups, kind: str = "aamp", p: float = 2.0, excl: Optional[int] = None,
+            P=None, I=None, stream=None, validate: bool = True):
+    """Profile over the diagonals of the listed groups (mp_anytime). With P
+    and I given (an earlier result for the same series and arguments) the
+    call resumes: rows keep the better of their entry and the new candidates,
+    and P, I are updated in place. Returns (P, I)."""
+    import numpy as np
+    import torch
+    T, n, N, P0, I0 = _series(T, m, validate)
+    resume = P is not None or I is not None
+    if resume:
+        if P is None or I is None:
+            raise ValueError("resume needs both P and I")
+        if (P.dtype != torch.float64 or I.dtype != torch.int64 or P.numel() != N
+                or I.numel() != N or not P.is_contiguous() or not I.is_contiguous()):
+            raise TypeError("P, I must be contiguous float64 / int64 tensors of N entries")
+    else:
+        P, I = P0, I0
+    g = np.ascontiguousarray(np.asarray(groups, dtype=np.int64))
+    if g.size and (g.min() < 0 or g.max() > 2**31 - 1):
+        raise ValueError("group index out of range")
+    g = g.astype(np.int32)
+    _check(load().mp_anytime(_KIND_OF[kind], T.data_ptr(), n, int(m), float(p), int(excl or 0),
+                             g.ctypes.data_as(ctypes.c_void_p) if g.size else None, int(g.size),
+                             1 if resume else 0, P.data_ptr(), I.data_ptr(), _stream(stream)))
+    return P, I
+
+
+class Anytime:
+    """Anytime profile of one series: the diagonal groups in a seeded random
+    order, swept a share of the pairs at a time. After advance(f) the profile
+    covers at least the fraction f of all admissible pairs; every P[i] is the
+    exact distance of (i, I[i]) and never increases with later calls.
+
+        a = Anytime(T, m=256, kind="acamp", seed=1)
+        P, I = a.advance(0.1)        # about 10 % of the pairs
+        P, I = a.advance(1.0)        # the exact profile
+    """
+
+    def __init__(self, T, m: int, kind: str = "aamp", p: float = 2.0,
+                 excl: Optional[int] = None, seed: int = 0):
+        import torch
+        self.T, self.m, self.kind, self.p, self.excl = T, m, kind, p, excl
+        self.order, self.cum = anytime_order(T.numel(), m, excl, seed)
+        self.done = 0                 # groups swept so far (a prefix of order)
+        N = T.numel() - m + 1
+        self.P = torch.full((N,), float("inf"), dtype=torch.float64, device=T.device)
+        self.I = torch.full((N,), -1, dtype=torch.int64, device=T.device)
+
+    @property
+    def covered(self) -> float:
+        """Fraction of the admissible pairs swept so far."""
+        total = int(self.cum[-1]) if self.cum.size else 0
+        return 1.0 if total == 0 else (int(self.cum[self.done - 1]) if self.done else 0) / total
+
+    def advance(self, fraction: float, stream=None):
+        import numpy as np
+        total = int(self.cum[-1]) if self.cum.size else 0
+        if fraction >= 1.0:
+            want = self.order.size
+        elif fraction <= 0.0:
+            want = self.done
+        else:   # the shortest prefix whose pairs reach the fraction
+            want = int(np.searchsorted(self.cum, fraction * total, side="left")) + 1
+        want = min(max(want, self.done), self.order.size)
+        if want > self.done:
+            anytime(self.T, self.m, self.order[self.done:want], self.kind, self.p, self.excl,
+                    P=self.P, I=self.I, stream=stream, validate=self.done == 0)
+            self.done = want
+        return self.P, self.I
 
 
 class Incremental:

@@ -87,6 +87,14 @@ struct Workspace {
     int64_t topk_mask_cap = 0;
     unsigned long long *topk_scratch = nullptr;
     int64_t topk_scratch_cap = 0;
+    // partial (anytime) sweeps: band slot -> group map, marks of the call's
+    // groups, and the call's own profile when it is merged into an earlier one
+    int32_t *any_map = nullptr;
+    uint8_t *any_ok = nullptr;
+    int64_t any_group_cap = 0;
+    double *any_P = nullptr;
+    int64_t *any_I = nullptr;
+    int64_t any_row_cap = 0;
     uint64_t generation = 1;           // bumped whenever the arrays above move
     int arch_ok = -1;                  // -1 unknown, 0 no, 1 gfx950
     int cus = 0;
@@ -114,9 +122,14 @@ void free_arrays(Workspace &w)
 void free_ws(Workspace &w)
 {
     free_arrays(w);
-    void *ptrs[] = {w.job1, w.row_base1, w.flag1, w.pivots1, w.band1, w.visits, w.topk_mask,
-                    w.topk_scratch};
+    void *ptrs[] = {w.job1,      w.row_base1,    w.flag1,   w.pivots1, w.band1, w.visits,
+                    w.topk_mask, w.topk_scratch, w.any_map, w.any_ok,  w.any_P, w.any_I};
     for (void *p : ptrs) hipFree(p);
+    w.any_map = nullptr;
+    w.any_ok = nullptr;
+    w.any_P = nullptr;
+    w.any_I = nullptr;
+    w.any_group_cap = w.any_row_cap = 0;
     w.visits = nullptr;
     w.topk_mask = nullptr;
     w.topk_scratch = nullptr;
@@ -211,6 +224,24 @@ int ensure_band1(Workspace &w, int64_t entries)
     return MP_OK;
 }
 
+int ensure_any(Workspace &w, int64_t groups, int64_t rows)
+{
+    if (w.any_group_cap < groups) {
+        const int64_t cap = std::max<int64_t>(groups, 1024);
+        w.any_group_cap = 0;
+        RC_TRY(grow(&w.any_map, cap, "workspace group map"));
+        RC_TRY(grow(&w.any_ok, cap, "workspace group marks"));
+        w.any_group_cap = cap;
+    }
+    if (w.any_row_cap < rows) {
+        w.any_row_cap = 0;
+        RC_TRY(grow(&w.any_P, rows, "workspace partial profile"));
+        RC_TRY(grow(&w.any_I, rows, "workspace partial profile"));
+        w.any_row_cap = rows;
+    }
+    return MP_OK;
+}
+
 int ensure_lib_stream(Workspace &w)
 {
     if (w.lib_stream) return MP_OK;
@@ -271,6 +302,25 @@ int64_t pair_count(int64_t N, int64_t excl)
     return k * (k + 1) / 2;
 }
 
+static_assert(ANY_GROUP == MP_ANYTIME_GROUP && ANY_GROUP == 64 * 8,
+              "a group of a partial sweep is one band of the FP64 band kernel");
+
+// Diagonal groups of a partial sweep: group g holds diagonals
+// [excl + g ANY_GROUP, excl + (g + 1) ANY_GROUP) that are below N.
+int64_t any_groups(int64_t N, int64_t excl)
+{
+    return N - excl > 0 ? (N - excl + ANY_GROUP - 1) / ANY_GROUP : 0;
+}
+
+// Pairs of group g: sum over its diagonals d of N - d.
+int64_t group_pairs(int64_t N, int64_t excl, int64_t g)
+{
+    const int64_t d0 = excl + g * ANY_GROUP, d1 = std::min<int64_t>(d0 + ANY_GROUP, N);
+    if (d1 <= d0) return 0;
+    const int64_t c = d1 - d0;
+    return c * N - c * (d0 + d1 - 1) / 2;
+}
+
 int32_t pclass_of(double p)
 {
     if (p == 1.0) return P_ONE;
@@ -287,6 +337,10 @@ struct Spec {
     double p;
     double *P;
     int64_t *I;
+    // partial sweep: the diagonal groups to visit (host array); ngroups < 0
+    // for a whole profile
+    const int32_t *groups = nullptr;
+    int64_t ngroups = -1;
 };
 
 int make_spec(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
@@ -470,17 +524,24 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         j.I = sp.I;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         const int64_t ndiag = s.N - s.excl;
+        const bool partial = sp.ngroups >= 0;     // FP64 band sweep over the listed groups
         // the sweep this job would join decides its band width
-        const bool single = want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
+        const bool single = !partial && want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
         const int64_t W = 64 * (single ? kd : 8);
         const bool has_band = (sel & SEL_BAND) || (sel == SEL_PGEN && all_pgen);
         bool band = has_band && ndiag >= W / 2 && choice != "simple";
         if (choice == "band" && has_band && ndiag > 0) band = true;
         if (ndiag <= 0) band = false;
+        if (partial) band = true;
         s.fp32 = (single && band) ? 1 : 0;
         int64_t rows = 0, nb = 0;
-        if (band) {
+        if (partial) {
+            nb = sp.ngroups;
+            for (int64_t t = 0; t < nb; ++t) rows += s.N - s.excl - (int64_t)sp.groups[t] * W;
+        } else if (band) {
             rows = band_rows_total(s.N, s.excl, W, &nb);
+        }
+        if (band) {
             j.band_cost = band_cost(sel, s.m);
             int64_t R = sp.R > 0 ? sp.R
                                  : (tu.R > 0 && s.fp32 == want32 ? tu.R : default_R(sel, s.fp32, s.m));
@@ -496,7 +557,10 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         }
         j.nbands = (int32_t)nb;
         L.sels |= sel;
-        L.pairs += pair_count(s.N, s.excl);
+        if (partial)
+            for (int64_t t = 0; t < nb; ++t) L.pairs += group_pairs(s.N, s.excl, sp.groups[t]);
+        else
+            L.pairs += pair_count(s.N, s.excl);
         L.items += nb + (band ? rows / j.seg_rows : 0);
         const int c = band ? (s.fp32 ? 1 : 0) : 2;
         cls[c].push_back(j);
@@ -913,6 +977,91 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
     return MP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// partial (anytime) sweeps: one series, the listed diagonal groups only
+// ---------------------------------------------------------------------------
+int run_anytime(int32_t kind, const double *T, int64_t n, int32_t m, double p, int32_t excl,
+                const int32_t *groups, int64_t ngroups, int32_t resume, double *P, int64_t *I,
+                void *stream)
+{
+    Spec sp;
+    RC_TRY(make_spec(T, n, m, kind, p, excl, 0, P, I, &sp));
+    if (ngroups < 0 || ngroups > INT32_MAX) return fail(MP_EINVAL, "ngroups out of range");
+    if (ngroups > 0 && !groups) return fail(MP_EINVAL, "null pointer argument");
+    if (resume != 0 && resume != 1) return fail(MP_EINVAL, "resume must be 0 or 1");
+    const uint32_t sel = sel_of(sp.kind, sp.pclass);
+    if (!(sel & SEL_BAND) && !(sel == SEL_PGEN && sp.p <= PGEN_BAND_MAX))
+        return fail(MP_EINVAL, "partial sweeps need a distance with a band kernel (p <= 6)");
+    const int64_t N = sp.n - sp.m + 1;
+    const int64_t G = any_groups(N, sp.excl);
+    std::vector<uint8_t> marks((size_t)std::max<int64_t>(G, 1), 0);
+    for (int64_t t = 0; t < ngroups; ++t) {
+        if (groups[t] < 0 || groups[t] >= G) return fail(MP_EINVAL, "group index out of range");
+        marks[(size_t)groups[t]] = 1;
+    }
+    sp.groups = groups;
+    sp.ngroups = ngroups;
+
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    Workspace *w = nullptr;
+    int dev = 0;
+    RC_TRY(get_ws(&w, &dev));
+    hipStream_t st = (hipStream_t)stream;
+    Layout L;
+    RC_TRY(make_layout({sp}, MP_FP64, Tuning(), *w, &L));
+    RC_TRY(ensure_arrays(*w, L.stream_total, L.key_total));
+    RC_TRY(ensure_band1(*w, L.band_entries));
+    RC_TRY(ensure_any(*w, std::max<int64_t>(ngroups, G), N));
+    bind(L, *w);
+    Job &J = L.jobs[0];
+    J.band_map = w->any_map;
+    J.group_ok = w->any_ok;
+    if (resume) {          // the call's own profile first, merged at the end
+        J.P = w->any_P;
+        J.I = w->any_I;
+    }
+    // pageable host sources: the copies have read them when they return
+    if (ngroups > 0)
+        HIP_TRY(hipMemcpyAsync(w->any_map, groups, (size_t)ngroups * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync");
+    if (G > 0)
+        HIP_TRY(hipMemcpyAsync(w->any_ok, marks.data(), (size_t)G, hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync");
+    Tables t;
+    t.jobs = w->job1;
+    t.row_base = w->row_base1;
+    t.band = w->band1;
+    t.flags = w->flag1;
+    t.pivots = w->pivots1;
+    const Batch b = make_batch(L, *w, t);
+
+    EvSet es;
+    bool prof = false;
+    RC_TRY(prof_begin(st, &es, &prof));
+    RowBase4 rb;
+    std::memset(&rb, 0, sizeof(rb));
+    rb.count = (int32_t)L.row_base.size();
+    for (int32_t k = 0; k < rb.count && k < 4; ++k) rb.v[k] = L.row_base[k];
+    HIP_TRY(launch_store_job(J, rb, w->job1, w->row_base1, st), "job table");
+    RC_TRY(enqueue(b, L, st, prof ? &es : nullptr));
+    if (resume) HIP_TRY(launch_any_merge(w->any_P, w->any_I, P, I, N, st), "merge launch");
+    if (prof) RC_TRY(finish_profile(es, b, L, st));
+    g_last_code = MP_OK;
+    return MP_OK;
+}
+
+// splitmix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): a Weyl sequence with step 0x9e3779b97f4a7c15
+// through a 64-bit mixing function.
+uint64_t splitmix64(uint64_t &state)
+{
+    uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
 int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,
               double *P_cat, int64_t *I_cat, void *stream)
 {
@@ -1056,6 +1205,48 @@ int mp_acamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precis
              double *P, int64_t *I, void *stream)
 {
     return run_series(T, n, m, ACAMP, 2.0, excl, precision, R, P, I, stream);
+}
+
+int mp_anytime(int32_t kind, const double *T, int64_t n, int32_t m, double p, int32_t excl,
+               const int32_t *groups, int64_t ngroups, int32_t resume, double *P, int64_t *I,
+               void *stream)
+{
+    return run_anytime(kind, T, n, m, p, excl, groups, ngroups, resume, P, I, stream);
+}
+
+int mp_anytime_groups(int64_t n, int32_t m, int32_t excl, int64_t *ngroups)
+{
+    if (!ngroups) return fail(MP_EINVAL, "null pointer argument");
+    if (n < 1 || n >= MP_MAX_N) return fail(MP_EINVAL, "n must satisfy 1 <= n < 2^31");
+    if (m < 1 || (int64_t)m > n) return fail(MP_EINVAL, "m must satisfy 1 <= m <= n");
+    const int64_t e = excl > 0 ? excl : (m + 3) / 4;
+    *ngroups = any_groups(n - m + 1, e);
+    g_last_code = MP_OK;
+    return MP_OK;
+}
+
+int mp_anytime_order(int64_t n, int32_t m, int32_t excl, uint64_t seed, int32_t *order,
+                     int64_t *cum_pairs)
+{
+    int64_t G = 0;
+    RC_TRY(mp_anytime_groups(n, m, excl, &G));
+    if (G > 0 && !order) return fail(MP_EINVAL, "null pointer argument");
+    const int64_t N = n - m + 1, e = excl > 0 ? excl : (m + 3) / 4;
+    // Fisher-Yates from the top; the draw for position k is the high word of
+    // a 64 x 64-bit product, uniform over [0, k] up to a 2^-64 bias
+    for (int64_t k = 0; k < G; ++k) order[k] = (int32_t)k;
+    uint64_t state = seed;
+    for (int64_t k = G - 1; k > 0; --k) {
+        const uint64_t r = splitmix64(state);
+        const int64_t u = (int64_t)(((unsigned __int128)r * (uint64_t)(k + 1)) >> 64);
+        std::swap(order[k], order[u]);
+    }
+    if (cum_pairs) {
+        int64_t run = 0;
+        for (int64_t k = 0; k < G; ++k) cum_pairs[k] = (run += group_pairs(N, e, order[k]));
+    }
+    g_last_code = MP_OK;
+    return MP_OK;
 }
 
 int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t precision,

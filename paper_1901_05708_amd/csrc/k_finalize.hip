@@ -292,8 +292,8 @@ __device__ __forceinline__ int lanes_below(unsigned long long mask)
 // queue is the wave's candidate list.
 template <int KIND, int PC>
 __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, int64_t pd_base,
-                                          const int32_t *pivots, int r, int64_t c, double *q,
-                                          int32_t *queue, int64_t &prev_row)
+                                          const int32_t *pivots, const uint8_t *gok, int r,
+                                          int64_t c, double *q, int32_t *queue, int64_t &prev_row)
 {
     const int lane = threadIdx.x;
     const unsigned long long mask = (1ull << s.gb) - 1ull;
@@ -352,6 +352,10 @@ __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, i
         for (int it = 0; it < FB_ITERS; ++it) {
             const int64_t j = c * FB_CHUNK + (int64_t)it * FB_WAVE + lane;
             bool cand = legal_pair(s, i, j);
+            if (gok && cand) {      // a partial sweep: only the call's diagonal groups
+                const int64_t d = i > j ? i - j : j - i;
+                cand = as_global(gok)[(d - s.excl) / ANY_GROUP] != 0;
+            }
             for (int k = 0; k < FB_PIVOTS; ++k) {
                 if (__ballot(cand) == 0) break;
                 if (pivots[k] < 0) continue;
@@ -407,12 +411,13 @@ __global__ void __launch_bounds__(FB_WAVE) k_fallback_scan(Batch b)
         const Series &s = J.s;
         if (c * FB_CHUNK >= s.N) continue;
         const int32_t *piv = fb.pivots + jb * FB_PIVOTS;
+        const uint8_t *gok = J.group_ok;
         switch (sel_of(s.kind, s.pclass)) {
-        case SEL_AAMP: scan_unit<AAMP, P_TWO>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
-        case SEL_ACAMP: scan_unit<ACAMP, P_TWO>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
-        case SEL_P1: scan_unit<PNORM, P_ONE>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
-        case SEL_P3: scan_unit<PNORM, P_THREE>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
-        default: scan_unit<PNORM, P_GENERIC>(s, fb, J.key_base, piv, r, c, q, queue, prev_row); break;
+        case SEL_AAMP: scan_unit<AAMP, P_TWO>(s, fb, J.key_base, piv, gok, r, c, q, queue, prev_row); break;
+        case SEL_ACAMP: scan_unit<ACAMP, P_TWO>(s, fb, J.key_base, piv, gok, r, c, q, queue, prev_row); break;
+        case SEL_P1: scan_unit<PNORM, P_ONE>(s, fb, J.key_base, piv, gok, r, c, q, queue, prev_row); break;
+        case SEL_P3: scan_unit<PNORM, P_THREE>(s, fb, J.key_base, piv, gok, r, c, q, queue, prev_row); break;
+        default: scan_unit<PNORM, P_GENERIC>(s, fb, J.key_base, piv, gok, r, c, q, queue, prev_row); break;
         }
     }
 }
@@ -449,6 +454,33 @@ __global__ void k_fallback_finish(Batch b)
         default: finish_row<PNORM, P_GENERIC>(J, key, i); break;
         }
     }
+}
+
+// Merge of a partial profile (Pn, In) into an earlier one (P, I) of the same
+// series: the smaller distance wins, equal distances keep the smaller index.
+// Both hold exact FP64 distances of their pairs (+inf / -1: none yet), so the
+// result is the profile over the union of the two sets of diagonals.
+__global__ void k_any_merge(const double *Pn, const int64_t *In, double *P, int64_t *I, int64_t N)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const int64_t jn = In[r];
+    if (jn < 0) return;
+    const double pn = Pn[r], po = P[r];
+    const int64_t jo = I[r];
+    if (jo < 0 || pn < po || (pn == po && jn < jo)) {
+        P[r] = pn;
+        I[r] = jn;
+    }
+}
+
+hipError_t launch_any_merge(const double *Pn, const int64_t *In, double *P, int64_t *I, int64_t N,
+                            hipStream_t st)
+{
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_any_merge, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, Pn, In,
+                       P, I, N);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Batch &b, hipStream_t st)

@@ -696,7 +696,8 @@ __global__ void __launch_bounds__(64)
         // up to the end of the share, the band, or the refresh interval,
         // whichever comes first; a share that ends among the restart positions
         // holds no row of the band.
-        const int64_t k_lo = uniform64((int64_t)s.excl + (int64_t)lo * RING);
+        const int64_t band = J.band_map ? (int64_t)load_uniform(&J.band_map[lo]) : (int64_t)lo;
+        const int64_t k_lo = uniform64((int64_t)s.excl + band * RING);
         const int64_t row0 = uniform64(bs[lo] + J.band_cost);   // position of row 0
         const int64_t i0 = uniform64(max(pos - row0, (int64_t)0));
         const int64_t lim = uniform64(min(pend, bs[lo + 1]) - row0);
@@ -721,8 +722,10 @@ __global__ void __launch_bounds__(64)
 }
 
 // Band table of every job (one block per job): bs[t] = row_base of the job +
-// positions of its bands before t, where band t has N - excl - t W rows and
-// takes band_cost more positions; the last entry bs[nbands] is the job's end.
+// positions of its bands before t, where band t covers diagonals from
+// excl + g W on (g = t, or band_map[t] in a partial sweep), has N - excl - g W
+// rows and takes band_cost more positions; the last entry bs[nbands] is the
+// job's end.
 __global__ void __launch_bounds__(1024) k_band_plan(Batch b)
 {
     __shared__ int64_t part[1024];
@@ -734,8 +737,10 @@ __global__ void __launch_bounds__(1024) k_band_plan(Batch b)
     const int t = threadIdx.x;
     const int per = (nb + 1023) / 1024;
     const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+    // band slot u covers diagonal group map[u] of a partial sweep, else u
+    const int32_t *map = J.band_map;
     int64_t sum = 0;
-    for (int u = b0; u < b1; ++u) sum += C + N - excl - (int64_t)u * W;
+    for (int u = b0; u < b1; ++u) sum += C + N - excl - (int64_t)(map ? map[u] : u) * W;
     part[t] = sum;
     __syncthreads();
     if (t == 0) {
@@ -751,7 +756,7 @@ __global__ void __launch_bounds__(1024) k_band_plan(Batch b)
     int64_t run = part[t];
     for (int u = b0; u < b1; ++u) {
         bs[u] = run;
-        run += C + N - excl - (int64_t)u * W;
+        run += C + N - excl - (int64_t)(map ? map[u] : u) * W;
     }
 }
 

@@ -114,7 +114,16 @@ struct Job {
     int32_t seg_rows;      // rows between exact restarts (refresh interval R)
     int32_t band_cost;     // positions a band takes in the row space before its rows
     int32_t pad1;
+    // Partial (anytime) sweeps; both null for a whole profile. band_map[t] is
+    // the diagonal group that band slot t covers (group g: diagonals
+    // [excl + g ANY_GROUP, excl + (g + 1) ANY_GROUP)); group_ok[g] != 0 marks
+    // the groups of the call, the only ones the exact search may score.
+    const int32_t *band_map;
+    const uint8_t *group_ok;
 };
+
+// Diagonals per group of a partial sweep: the band of the FP64 band kernel.
+constexpr int64_t ANY_GROUP = 512;
 
 // Every array the kernels touch lives in device global memory. Addressing it
 // through the global address space makes the compiler emit global_* rather
@@ -215,6 +224,8 @@ hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_la
 hipError_t launch_sweep_simple(const Batch &b, hipStream_t st);
 hipError_t launch_finalize(const Batch &b, hipStream_t st);
 hipError_t launch_fallback(const Batch &b, hipStream_t st);
+hipError_t launch_any_merge(const double *Pn, const int64_t *In, double *P, int64_t *I, int64_t N,
+                            hipStream_t st);
 
 // Motifs / discords of a computed profile (k rounds of 3 small kernels).
 // scratch holds 3k u64, mask N bytes.

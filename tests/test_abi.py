@@ -138,3 +138,69 @@ def test_strerror_never_null(lib):
 
 def test_profile_read_rejects_null(lib):
     assert lib.mp_profile_read(None) == mp.MP_EINVAL
+
+
+def test_anytime_arguments_rejected_without_gpu(lib):
+    dummy = ctypes.c_void_p(16)
+    g = (ctypes.c_int32 * 2)(0, 1)
+    n, m = 5000, 32                       # N = 4969, excl 8: 10 groups
+    ok = [mp.KIND_AAMP, dummy, n, m, 2.0, 0, g, 2, 0, dummy, dummy, None]
+
+    def call(**kw):
+        a = list(ok)
+        for k, v in kw.items():
+            a[int(k[1:])] = v
+        return lib.mp_anytime(*a)
+
+    assert call(a1=None) == mp.MP_EINVAL                          # null T
+    assert call(a3=0) == mp.MP_EINVAL                             # m < 1
+    assert call(a0=9) == mp.MP_EINVAL                             # bad kind
+    assert call(a0=mp.KIND_PNORM, a4=7.0) == mp.MP_EINVAL         # p > 6: no band kernel
+    assert call(a7=-1) == mp.MP_EINVAL                            # ngroups < 0
+    assert call(a6=None) == mp.MP_EINVAL                          # null groups
+    assert call(a8=2) == mp.MP_EINVAL                             # resume not 0 / 1
+    bad = (ctypes.c_int32 * 1)(10)
+    assert call(a6=bad, a7=1) == mp.MP_EINVAL                     # group past the last
+    neg = (ctypes.c_int32 * 1)(-1)
+    assert call(a6=neg, a7=1) == mp.MP_EINVAL
+    G = ctypes.c_int64()
+    assert lib.mp_anytime_groups(n, m, 0, None) == mp.MP_EINVAL
+    assert lib.mp_anytime_groups(n, 0, 0, ctypes.byref(G)) == mp.MP_EINVAL
+    assert lib.mp_anytime_groups(10, 11, 0, ctypes.byref(G)) == mp.MP_EINVAL
+    assert lib.mp_anytime_order(n, m, 0, 1, None, None) == mp.MP_EINVAL
+
+
+def test_anytime_groups_and_order_on_host(lib):
+    """Host-only helpers: the group count, the order is a permutation fixed by
+    the seed, and the cumulative pairs count the admissible pairs of each
+    prefix (checked by summing N - d over the prefix's diagonals)."""
+    import numpy as np
+    for n, m, excl in ((5000, 32, 0), (2000, 100, 1), (1100, 64, 0), (700, 64, 700)):
+        N = n - m + 1
+        e = excl or mp.default_excl(m)
+        G = mp.anytime_groups(n, m, excl)
+        assert G == (max(N - e, 0) + 511) // 512
+        order, cum = mp.anytime_order(n, m, excl, seed=7)
+        assert sorted(order.tolist()) == list(range(G))
+        o2, c2 = mp.anytime_order(n, m, excl, seed=7)
+        assert np.array_equal(order, o2) and np.array_equal(cum, c2)
+        if G:
+            assert cum[-1] == mp.pair_count(n, m, e)
+            want, run = [], 0
+            for g in order:
+                d = np.arange(e + 512 * g, min(e + 512 * (g + 1), N))
+                run += int((N - d).sum())
+                want.append(run)
+            assert cum.tolist() == want
+    # different seeds give different orders; seed 0 is not the identity
+    a, _ = mp.anytime_order(200000, 64, 0, seed=1)
+    b, _ = mp.anytime_order(200000, 64, 0, seed=2)
+    c, _ = mp.anytime_order(200000, 64, 0, seed=0)
+    assert not np.array_equal(a, b)
+    assert not np.array_equal(c, np.arange(c.size))
+    # roughly uniform: each group lands in the first half about half the time
+    first = np.zeros(a.size)
+    for s in range(200):
+        o, _ = mp.anytime_order(200000, 64, 0, seed=100 + s)
+        first[o[: o.size // 2]] += 1
+    assert 0.35 < first.mean() / 200 < 0.65 and first.min() > 50 and first.max() < 150
