@@ -336,6 +336,48 @@ def incremental(mp, h, torch):
             "N": N}
 
 
+def anytime_curve(mp, h, torch):
+    """Anytime sweep of the headline series: the diagonal groups in a seeded
+    random order, advanced to 1 %, 5 %, 25 % and 100 % of the pairs. Reports
+    the host wall time of each advance, and the share of rows whose value
+    already equals the full profile's (relative 1e-9) at each point."""
+    import numpy as np
+    T = torch.as_tensor(h["T"], device="cuda")
+    m, excl = h["m"], h["excl"]
+    Pf = torch.as_tensor(h["fp64"]["P"], device="cuda")
+    fin = torch.isfinite(Pf)
+    mp.Anytime(T, m, kind="acamp", excl=excl, seed=1).advance(0.02)     # warm
+    torch.cuda.synchronize()
+    a = mp.Anytime(T, m, kind="acamp", excl=excl, seed=1)
+    torch.cuda.synchronize()
+    points, total_ms, prev_pairs = [], 0.0, 0
+    total = int(a.cum[-1])
+    for f in (0.01, 0.05, 0.25, 1.0):
+        t0 = time.perf_counter()
+        P, _ = a.advance(f)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        total_ms += ms
+        pairs = int(a.cum[a.done - 1])
+        # the parity tests' tolerance: 1e-9 relative, 1e-6 absolute (ACAMP)
+        exact = torch.isfinite(P) & (P <= Pf * (1 + 1e-9) + 1e-6)
+        both = fin & torch.isfinite(P) & (Pf > 0)
+        ratio = (P[both] / Pf[both]).cpu().numpy()
+        points.append({"fraction": round(pairs / total, 4), "groups": int(a.done),
+                       "step_ms": round(ms, 3), "step_gpairs_per_s":
+                       round((pairs - prev_pairs) / ms / 1e6, 1),
+                       "rows_exact": round(float((exact & fin).sum()) / float(fin.sum()), 4),
+                       "p_ratio_median": round(float(np.median(ratio)), 4) if ratio.size else None,
+                       "p_ratio_p90": round(float(np.quantile(ratio, 0.9)), 4) if ratio.size
+                       else None})
+        prev_pairs = pairs
+    return {"groups": int(a.order.size), "seed": 1, "points": points,
+            "total_ms": round(total_ms, 3),
+            "note": "host wall time per advance (one mp_anytime call each, resumed); rows_exact: "
+                    "share of rows whose P already equals the full profile's; p_ratio: P over "
+                    "the full profile's P (median, 90th percentile)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -428,6 +470,7 @@ def main():
     out["topk"] = {"k": 10, "excl": h["m"], **tk,
                    "note": "host wall time per call including the count read-back"}
     out["incremental"] = incremental(mp, h, torch)
+    out["anytime"] = anytime_curve(mp, h, torch)
     if not args.no_batch:
         out["batch"] = batch_workload(args, mp, W, torch)
     if args.configs:
