@@ -378,6 +378,36 @@ def anytime_curve(mp, h, torch):
                     "the full profile's P (median, 90th percentile)"}
 
 
+def fcmp_variant(args, mp, h, torch):
+    """The headline series with the sweep comparing pairs on the F of
+    Sec. 4.3 (mp_acamp_fcmp), timed like the headline at the refresh interval
+    the headline run chose, against the headline's own FP64 figures (pairs
+    compared on rho): ms per call, sweep ms, and index agreement."""
+    Td = torch.as_tensor(h["T"], device="cuda")
+    m, excl, rho = h["m"], h["excl"], h["fp64"]
+    R = rho["refresh_rows"]
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def step():
+        out["PI"] = mp.acamp_fcmp(Td, m, excl=excl, R=R, stream=stream, validate=False)
+
+    mp.acamp_fcmp(Td, m, excl=excl, R=R, stream=stream)
+    torch.cuda.synchronize()
+    mp.set_profiling(True)
+    ms, med = timed(step, max(3, args.steps // 3), args.warmup, stream)
+    prof = mp.profile_read()
+    mp.set_profiling(False)
+    calls = max(1, prof["calls"])
+    sweep = prof["ms_sweep"] / calls
+    agree = float((out["PI"][1].cpu().numpy() == rho["I"]).mean())
+    return {"value": round(h["pairs"] / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
+            "sweep_ms": round(sweep, 4), "rho_value": round(rho["value"], 3),
+            "rho_sweep_ms": round(rho["sweep_ms"], 4),
+            "sweep_ratio_vs_rho": round(sweep / rho["sweep_ms"], 4), "refresh_rows": R,
+            "index_agreement": round(agree, 6)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -471,6 +501,7 @@ def main():
                    "note": "host wall time per call including the count read-back"}
     out["incremental"] = incremental(mp, h, torch)
     out["anytime"] = anytime_curve(mp, h, torch)
+    out["acamp_fcmp"] = fcmp_variant(args, mp, h, torch)
     if not args.no_batch:
         out["batch"] = batch_workload(args, mp, W, torch)
     if args.configs:

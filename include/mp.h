@@ -103,11 +103,26 @@ int mp_pnorm(const double *T, int64_t n, int32_t m, double p, int32_t excl,
  * mp_acamp -- z-normalized Euclidean matrix profile (ACAMP, Sec. 4).
  * Distance: DZ_{i,j} = sqrt(sum_l ((t_{i+l}-mu_i)/s_i - (t_{j+l}-mu_j)/s_j)^2)
  * (Def. 2.7, Eq. 3) with population standard deviations; equivalently
- * DZ^2 = 2m(1 - rho_{i,j}) (Lemma 3, Eq. 5). A window whose samples are all
+ * DZ^2 = 2m(1 - rho_{i,j}) (Lemma 3, Eq. 8). A window whose samples are all
  * equal has s = 0 and infinite distance to everything (Sec. 1).
  */
 int mp_acamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precision,
              int32_t R, double *P, int64_t *I, void *stream);
+
+/*
+ * mp_acamp_fcmp -- mp_acamp in FP64 with the sweep comparing pairs on the
+ * quantity F of Sec. 4.3 (Eq. 9) instead of rho. For two windows,
+ * F = -m^2 rho |rho|: F grows exactly when DZ does, and
+ * DZ^2 = 2m + 2 sign(F) sqrt|F| (Eq. 10, read as the squared distance). The
+ * band sweep keys each pair on 1 + F / m^2 = 1 - rho |rho|, one multiply more
+ * per pair than mp_acamp's 1 - rho; winners are rescored exactly as there,
+ * so (P, I) agree with mp_acamp up to near ties. Series with fewer than 256
+ * admissible diagonals run the simple kernel, which compares on rho (the same
+ * order). Arguments, layout and errors as for mp_acamp (no precision
+ * argument: FP64 only).
+ */
+int mp_acamp_fcmp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t R, double *P,
+                  int64_t *I, void *stream);
 
 /*
  * One series of a batch. Offsets are in elements. Series b occupies

@@ -27,7 +27,8 @@ MP_FP64, MP_FP32_REFRESH = 0, 1
 KIND_AAMP, KIND_PNORM, KIND_ACAMP = 0, 1, 2
 FP32_RTOL = 1e-4
 
-EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_batch", "mp_topk", "mp_anytime",
+EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_acamp_fcmp", "mp_batch", "mp_topk",
+            "mp_anytime",
             "mp_anytime_groups", "mp_anytime_order", "mp_inc_create", "mp_inc_append",
             "mp_inc_state", "mp_inc_read", "mp_inc_destroy", "mp_strerror", "mp_release",
             "mp_set_profiling", "mp_profile_read")
@@ -76,6 +77,8 @@ def load(path: str = LIB_PATH):
     lib.mp_aamp.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp]
     lib.mp_pnorm.argtypes = [vp, i64, i32, dbl, i32, i32, i32, vp, vp, vp]
     lib.mp_acamp.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp]
+    lib.mp_acamp_fcmp.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
+    lib.mp_acamp_fcmp.restype = ctypes.c_int
     lib.mp_batch.argtypes = [vp, ctypes.POINTER(MpJob), i32, i32, vp, vp, vp]
     for f in (lib.mp_aamp, lib.mp_pnorm, lib.mp_acamp, lib.mp_batch):
         f.restype = ctypes.c_int
@@ -181,6 +184,16 @@ def acamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, s
     T, n, N, P, I = _series(T, m, validate)
     _check(load().mp_acamp(T.data_ptr(), n, m, excl or 0, _prec(precision), R,
                            P.data_ptr(), I.data_ptr(), _stream(stream)))
+    return P, I
+
+
+def acamp_fcmp(T, m: int, excl: Optional[int] = None, R: int = 0, stream=None,
+               validate: bool = True):
+    """z-normalized matrix profile with the sweep comparing pairs on the F
+    of Sec. 4.3 instead of rho (mp_acamp_fcmp; FP64). Returns (P, I)."""
+    T, n, N, P, I = _series(T, m, validate)
+    _check(load().mp_acamp_fcmp(T.data_ptr(), n, m, excl or 0, R, P.data_ptr(), I.data_ptr(),
+                                _stream(stream)))
     return P, I
 
 

@@ -341,6 +341,7 @@ struct Spec {
     // for a whole profile
     const int32_t *groups = nullptr;
     int64_t ngroups = -1;
+    int32_t fcmp = 0;          // ACAMP compared on F (Sec. 4.3), FP64 band sweep
 };
 
 int make_spec(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
@@ -526,7 +527,9 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         const int64_t ndiag = s.N - s.excl;
         const bool partial = sp.ngroups >= 0;     // FP64 band sweep over the listed groups
         // the sweep this job would join decides its band width
-        const bool single = !partial && want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
+        s.fcmp = sp.fcmp;
+        const bool single =
+            !partial && !sp.fcmp && want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
         const int64_t W = 64 * (single ? kd : 8);
         const bool has_band = (sel & SEL_BAND) || (sel == SEL_PGEN && all_pgen);
         bool band = has_band && ndiag >= W / 2 && choice != "simple";
@@ -590,7 +593,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
             L.stream_total += s.N + STREAM_PAD;
             L.max_N = std::max(L.max_N, s.N);
             L.max_stream = std::max(L.max_stream, s.N + STREAM_PAD);
-            if (c < 2) L.g[c].sels |= sel_of(s.kind, s.pclass);
+            if (c < 2) L.g[c].sels |= sel_of(s.kind, s.pclass) | (s.fcmp ? SEL_FCMP : 0u);
             L.jobs.push_back(j);
         }
         if (c < 2) {
@@ -926,11 +929,13 @@ int tuning_for(const std::vector<Spec> &specs, const mp_job *jobs, int32_t njobs
 // single series: a batch of one job, tables written on the stream
 // ---------------------------------------------------------------------------
 int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
-               int32_t precision, int32_t R, double *P, int64_t *I, void *stream)
+               int32_t precision, int32_t R, double *P, int64_t *I, void *stream,
+               int32_t fcmp = 0)
 {
     Spec sp;
     RC_TRY(make_spec(T, n, m, kind, p, excl, R, P, I, &sp));
     RC_TRY(check_precision(precision));
+    sp.fcmp = fcmp;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     Workspace *w = nullptr;
     int dev = 0;
@@ -1205,6 +1210,12 @@ int mp_acamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precis
              double *P, int64_t *I, void *stream)
 {
     return run_series(T, n, m, ACAMP, 2.0, excl, precision, R, P, I, stream);
+}
+
+int mp_acamp_fcmp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t R, double *P,
+                  int64_t *I, void *stream)
+{
+    return run_series(T, n, m, ACAMP, 2.0, excl, MP_FP64, R, P, I, stream, 1);
 }
 
 int mp_anytime(int32_t kind, const double *T, int64_t n, int32_t m, double p, int32_t excl,

@@ -76,6 +76,7 @@ __device__ __forceinline__ Series inc_series(const IncState &s)
     v.xf = v.yf = v.zf = nullptr;
     v.fp32 = 0;
     v.force_fb = 0;
+    v.fcmp = 0;
     return v;
 }
 

@@ -234,6 +234,20 @@ constexpr int stage_doubles()
 // [i0, i1). ring (NF x RING entries) and rowbuf (NRB x 64) are the wave's LDS;
 // stage (stage_doubles<KD>() entries) overlays them while the first row is
 // computed.
+// ACAMP key of a pair from its centred cross sum S, invn_i (ri) and -invn_j
+// (cj). With q = S ri cj = -rho the default key is 1 - rho. The comparator
+// of Sec. 4.3, F = -m^2 rho |rho|, orders pairs as the distance does; its key
+// 1 + F / m^2 = 1 - rho |rho| = fma(q, |q|, 1) costs one multiply more.
+template <int PC, typename F>
+__device__ __forceinline__ F acamp_key(F S, F ri, F cj)
+{
+    if (PC == P_FCMP) {
+        const F q = S * ri * cj;
+        return fma(q, fabs(q), (F)1);
+    }
+    return fma(S * ri, cj, (F)1);
+}
+
 template <int KIND, int PC, int KD, typename F, bool COUNT>
 __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, const int64_t i0,
                                           const int64_t i1, F *ring, F *rowbuf, double *stage,
@@ -490,7 +504,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
             const int64_t jb = cb + (int64_t)KD * lane;
 #pragma unroll
             for (int d = 0; d < KD; ++d)
-                v[d] = (KIND == ACAMP) ? fma(S[d] * rinv0, sz[jb + d], (F)1) : S[d];
+                v[d] = (KIND == ACAMP) ? acamp_key<PC, F>(S[d], rinv0, sz[jb + d]) : S[d];
             reduce_step(-1, 0, v);
         }
         flush_cols(0, 1);   // column 0 has only the first row's pair
@@ -578,8 +592,8 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                     } else {
                         S[d] = fma(rx, cy[sl], S[d]);
                         S[d] = fma(cx[sl], ry, S[d]);
-                        // 1 - rho, with cz = -invn_j: the minimised quantity
-                        v[d] = fma(S[d] * rinv, cz[sl], (F)1);
+                        // 1 - rho (or 1 - rho |rho|), with cz = -invn_j
+                        v[d] = acamp_key<PC, F>(S[d], rinv, cz[sl]);
                     }
                 }
                 reduce_step(tau, q + 1, v);
@@ -711,7 +725,8 @@ __global__ void __launch_bounds__(64)
         if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
             band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
-            band_item<ACAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
+            band_item<ACAMP, (SELS & SEL_FCMP) ? P_FCMP : P_TWO, KD, F, COUNT>(
+                s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_P1) && sel == SEL_P1)
             band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
@@ -779,6 +794,10 @@ const void *band_kernel(uint32_t sels, bool count)
         if (sels == SEL_PGEN)
             return count ? (const void *)k_sweep_band<SEL_PGEN, KD, F, true>
                          : (const void *)k_sweep_band<SEL_PGEN, KD, F, false>;
+        // ACAMP keyed on F: launches of such jobs alone (pair counting runs
+        // the mixed kernel, which visits the same pairs)
+        if (sels == (SEL_ACAMP | SEL_FCMP) && !count)
+            return (const void *)k_sweep_band<SEL_ACAMP | SEL_FCMP, KD, F, false>;
     }
     if (count) return (const void *)k_sweep_band<SEL_BAND, KD, F, true>;
     switch (sels & SEL_BAND) {

@@ -10,7 +10,7 @@
 //
 //   AAMP / p-norm : x = the pre-root sum S (Sec. 3.2: compare squares,
 //                   take the root once at the end)
-//   ACAMP         : x = 1 - rho, so DZ^2 = 2m x (Lemma 3, Eq. 5)
+//   ACAMP         : x = 1 - rho, so DZ^2 = 2m x (Lemma 3, Eq. 8)
 //
 // ~0 (all ones) means "no candidate".
 #pragma once

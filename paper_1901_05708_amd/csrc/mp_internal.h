@@ -14,6 +14,9 @@ enum Kind : int32_t { AAMP = 0, PNORM = 1, ACAMP = 2 };
 // p-norm specialisations: p = 2 runs the Euclidean kernels, p = 1 and p = 3
 // have closed-form power terms, any other p goes through pow().
 enum PClass : int32_t { P_GENERIC = 0, P_ONE = 1, P_TWO = 2, P_THREE = 3 };
+// Template value of the band kernel only (never a job's pclass): its ACAMP
+// pairs are keyed on the comparator F of Sec. 4.3 instead of 1 - rho.
+constexpr int P_FCMP = 4;
 
 // Extra stream entries past N so that sweeps may read a little beyond the last
 // window (tail rows of a segment, the last diagonals of a band) without any
@@ -45,7 +48,7 @@ struct Series {
     int32_t excl;
     double p;
     int32_t gb;            // index bits of a global key
-    int32_t pad0;
+    int32_t fcmp;          // ACAMP: the band sweep compares pairs on F (Sec. 4.3)
     // Difference streams, N + STREAM_PAD entries each.
     //   AAMP:  x = u_j = t[j+m-1] - t[j-1],  y = v_j = t[j+m-1] + t[j-1]
     //   PNORM: x = a_j = t[j+m-1],           y = b_j = t[j-1]
@@ -186,6 +189,7 @@ enum Sel : uint32_t {
     SEL_P1 = 4,
     SEL_P3 = 8,
     SEL_PGEN = 16,
+    SEL_FCMP = 32,     // a launch flag, not a distance: its ACAMP jobs are keyed on F
 };
 
 __host__ __device__ inline uint32_t sel_of(int32_t kind, int32_t pclass)

@@ -56,6 +56,10 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.mp_pnorm(dummy, 100, 10, 0.5, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
     assert lib.mp_pnorm(dummy, 100, 10, float("inf"), 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
     assert lib.mp_pnorm(dummy, 100, 10, float("nan"), 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    # the F comparator variant: the same argument rules
+    assert lib.mp_acamp_fcmp(None, 100, 10, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_acamp_fcmp(dummy, 100, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_acamp_fcmp(dummy, 100, 10, 0, -1, dummy, dummy, None) == mp.MP_EINVAL
     msg = lib.mp_strerror(mp.MP_EINVAL).decode()
     assert "invalid argument" in msg
     # batch: bad job table
