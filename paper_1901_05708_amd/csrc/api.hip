@@ -467,6 +467,10 @@ struct Layout {
     int64_t pairs = 0, items = 0;
     int32_t R_report = 0;
     bool count = false;                  // pair-visit counting (test mode)
+    // Whether a row can reach the exact search: an ACAMP job (a constant
+    // partner can win the sweep), an FP32 sweep (its self-check) or the test
+    // hook. FP64 Euclidean and p-norm sweeps key admissible pairs only.
+    bool exact_search = false;
 };
 
 int env_int(const char *name, int dflt)
@@ -521,6 +525,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         s.p = sp.p;
         s.gb = index_bits(s.N);
         s.force_fb = force_fb;
+        if (force_fb) L.exact_search = true;
         j.P = sp.P;
         j.I = sp.I;
         const uint32_t sel = sel_of(s.kind, s.pclass);
@@ -537,6 +542,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         if (ndiag <= 0) band = false;
         if (partial) band = true;
         s.fp32 = (single && band) ? 1 : 0;
+        if (s.fp32 || s.kind == ACAMP) L.exact_search = true;
         int64_t rows = 0, nb = 0;
         if (partial) {
             nb = sp.ngroups;
@@ -707,7 +713,7 @@ int enqueue(const Batch &b, const Layout &L, hipStream_t st, EvSet *es)
     if (L.simple_diag > 0) HIP_TRY(launch_sweep_simple(b, st), "sweep launch");
     if (es) HIP_TRY(hipEventRecord(es->ev[2], st), "hipEventRecord");
     HIP_TRY(launch_finalize(b, st), "finalize launch");
-    HIP_TRY(launch_fallback(b, st), "fallback launch");
+    if (L.exact_search) HIP_TRY(launch_fallback(b, st), "fallback launch");
     return MP_OK;
 }
 

@@ -743,36 +743,45 @@ __global__ void __launch_bounds__(64)
 // job's end.
 __global__ void __launch_bounds__(1024) k_band_plan(Batch b)
 {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t wtot[16];
     const Job J = load_uniform(&b.jobs[blockIdx.x]);
     const int64_t base = J.row_start;
     const int64_t N = J.s.N, excl = J.s.excl, W = b.band_width, C = J.band_cost;
     const int nb = J.nbands;
     int64_t *bs = b.band_start + J.band_base;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int per = (nb + 1023) / 1024;
     const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
     // band slot u covers diagonal group map[u] of a partial sweep, else u
     const int32_t *map = J.band_map;
     int64_t sum = 0;
     for (int u = b0; u < b1; ++u) sum += C + N - excl - (int64_t)(map ? map[u] : u) * W;
-    part[t] = sum;
+    // exclusive prefix of the threads' sums: inclusive scans within each
+    // wave, then over the 16 wave totals
+    int64_t x = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wtot[wid] = x;
     __syncthreads();
-    if (t == 0) {
-        int64_t run = base;
-        for (int u = 0; u < 1024; ++u) {
-            const int64_t v = part[u];
-            part[u] = run;
-            run += v;
+    if (wid == 0) {
+        int64_t w = lane < 16 ? wtot[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const int64_t y = __shfl_up(w, off, 64);
+            if (lane >= off) w += y;
         }
-        bs[nb] = run;
+        if (lane < 16) wtot[lane] = w;
     }
     __syncthreads();
-    int64_t run = part[t];
+    int64_t run = base + (wid ? wtot[wid - 1] : 0) + x - sum;
     for (int u = b0; u < b1; ++u) {
         bs[u] = run;
         run += C + N - excl - (int64_t)(map ? map[u] : u) * W;
     }
+    if (t == 1023) bs[nb] = base + wtot[15];
 }
 
 hipError_t launch_plan(const Batch &b, hipStream_t st)
