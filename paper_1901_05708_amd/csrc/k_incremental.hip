@@ -13,11 +13,12 @@
 //  * k_inc_stats: window statistics (ACAMP) of the new windows, key reset.
 //  * k_inc_columns: one thread per diagonal walks the chunk's new columns,
 //    starting from the stored last column or, at a refresh and on diagonals
-//    that begin inside the chunk, from an exact FP64 sum; rows whose packed
-//    key improves are flagged. All threads take the same column at a step,
-//    so its key is reduced over the wave before its one atomic.
-//  * k_inc_rescore: flagged rows and the new windows take their exact FP64
-//    distance (as the one-shot path does).
+//    that begin inside the chunk, from an exact FP64 sum. Row keys travel
+//    up the lanes of a wave with their row and leave it with one atomic;
+//    all threads take the same column at a step, so its key is reduced over
+//    the wave before its one atomic.
+//  * k_inc_rescore: the new windows and the old rows whose key changed take
+//    their exact FP64 distance (as the one-shot path does).
 // A first load, and any append longer than a fraction of the series, runs the
 // one-shot pipeline instead and rebuilds the state from its profile.
 #include <algorithm>
@@ -46,7 +47,6 @@ struct IncState {
     double *mu;
     double *invn;
     uint8_t *isconst;
-    uint8_t *dirty;
     const double *col_old;     // S(r, w0 - 1) for rows r <= w0 - 1 - excl
     double *col_new;           // S(r, w1) after the chunk
     int64_t N;
@@ -87,7 +87,6 @@ __global__ void k_inc_stats(IncState s, int64_t w0, int64_t w1)
     const int64_t w = w0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w > w1) return;
     s.keys[w] = KEY_NONE;
-    s.dirty[w] = 0;
     if (s.kind != ACAMP) return;
     const gptr<double> x = as_global(s.T) + w;
     const int m = s.m;
@@ -130,39 +129,120 @@ __device__ double inc_start(const IncState &s, int64_t i, int64_t j)
     return acc;
 }
 
-// Update from (i - 1, j - 1) to (i, j).
-template <int KIND, int PC>
-__device__ __forceinline__ double inc_step(const IncState &s, int64_t i, int64_t j)
+// Operands of the pair (i, j): those of the update from (i - 1, j - 1) and,
+// for ACAMP, those of its key.
+struct IncOps {
+    double ai, bi, aj, bj;     // t[i+m-1], t[i-1], t[j+m-1], t[j-1]
+    double mi, mi1, mj, mj1;   // ACAMP: mu_i, mu_{i-1}, mu_j, mu_{j-1}
+    double ni, nj;             // ACAMP: invn_i, invn_j
+    bool ci, cj;               // ACAMP: constant windows
+};
+
+// Loads them. Rows outside [1, N - 1] (a lane whose diagonal has no row at
+// this column yet, or row 0, which only takes a start value) read row 1 or
+// N - 1 for the update operands and row 0 or N - 1 for the key operands:
+// in-bounds values that are never used for the update. Columns satisfy
+// 1 <= j < N.
+template <int KIND>
+__device__ __forceinline__ IncOps inc_load(const IncState &s, int64_t i, int64_t j)
 {
     const gptr<double> T = as_global(s.T);
+    const int64_t iu = min(max(i, (int64_t)1), s.N - 1);
+    const int64_t ik = min(max(i, (int64_t)0), s.N - 1);
     const int m = s.m;
-    const double ai = T[i + m - 1], aj = T[j + m - 1], bi = T[i - 1], bj = T[j - 1];
-    if (KIND == AAMP) return fma(ai - aj, ai - aj, -(bi - bj) * (bi - bj));
-    if (KIND == PNORM) return pn_term<PC>(ai - aj, s.p) - pn_term<PC>(bi - bj, s.p);
-    const double dfi = 0.5 * (ai - bi), dfj = 0.5 * (aj - bj);
-    const double dgi = (ai - s.mu[i]) + (bi - s.mu[i - 1]);
-    const double dgj = (aj - s.mu[j]) + (bj - s.mu[j - 1]);
+    IncOps o;
+    o.ai = T[iu + m - 1];
+    o.bi = T[iu - 1];
+    o.aj = T[j + m - 1];
+    o.bj = T[j - 1];
+    if (KIND == ACAMP) {
+        const gptr<double> mu = as_global(s.mu);
+        o.mi = mu[iu];
+        o.mi1 = mu[iu - 1];
+        o.mj = mu[j];
+        o.mj1 = mu[j - 1];
+        o.ni = as_global(s.invn)[ik];
+        o.nj = as_global(s.invn)[j];
+        o.ci = as_global(s.isconst)[ik] != 0;
+        o.cj = as_global(s.isconst)[j] != 0;
+    }
+    return o;
+}
+
+// Update from (i - 1, j - 1) to (i, j).
+template <int KIND, int PC>
+__device__ __forceinline__ double inc_update(const IncOps &o, double p)
+{
+    if (KIND == AAMP) return fma(o.ai - o.aj, o.ai - o.aj, -(o.bi - o.bj) * (o.bi - o.bj));
+    if (KIND == PNORM) return pn_term<PC>(o.ai - o.aj, p) - pn_term<PC>(o.bi - o.bj, p);
+    const double dfi = 0.5 * (o.ai - o.bi), dfj = 0.5 * (o.aj - o.bj);
+    const double dgi = (o.ai - o.mi) + (o.bi - o.mi1);
+    const double dgj = (o.aj - o.mj) + (o.bj - o.mj1);
     return fma(dfi, dgj, dfj * dgi);
 }
 
-// Smallest key over the 64 lanes of the wave (every lane takes part).
+template <int KIND, int PC>
+__device__ __forceinline__ double inc_step(const IncState &s, int64_t i, int64_t j)
+{
+    return inc_update<KIND, PC>(inc_load<KIND>(s, i, j), s.p);
+}
+
+// Column-walk steps whose operands are loaded together before any is used.
+constexpr int INC_BATCH = 4;
+
+// x combined with its DPP-moved copy (ctrl, row mask); lanes outside the row
+// mask, and lanes without a source, keep x.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_min_u64(unsigned long long x)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)x, (int)(uint32_t)x, CTRL, ROWS,
+                                               0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(x >> 32), (int)(uint32_t)(x >> 32),
+                                               CTRL, ROWS, 0xF, false);
+    const unsigned long long y = ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+    return y < x ? y : x;
+}
+
+// Smallest key over the 64 lanes of the wave, in lane 63 (every lane takes
+// part): within each row of 16 lanes by quad swaps and the half-row and row
+// mirrors, then across rows by the row broadcasts of lanes 15 and 31.
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const unsigned long long y = __shfl_xor(x, off, 64);
-        x = y < x ? y : x;
-    }
+    x = dpp_min_u64<0xB1, 0xF>(x);     // quad_perm [1,0,3,2]
+    x = dpp_min_u64<0x4E, 0xF>(x);     // quad_perm [2,3,0,1]
+    x = dpp_min_u64<0x141, 0xF>(x);    // row_half_mirror
+    x = dpp_min_u64<0x140, 0xF>(x);    // row_mirror
+    x = dpp_min_u64<0x142, 0xA>(x);    // row_bcast:15 into rows 1 and 3
+    x = dpp_min_u64<0x143, 0xC>(x);    // row_bcast:31 into rows 2 and 3
     return x;
+}
+
+// The row key of lane l - 1 moves to lane l (lane 0 receives none).
+__device__ __forceinline__ unsigned long long shift_up_none(unsigned long long x)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)(uint32_t)x, 0x138, 0xF, 0xF,
+                                               false);
+    const int hi = __builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)(uint32_t)(x >> 32), 0x138,
+                                               0xF, 0xF, false);      // 0x138: wave_shr:1
+    return ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Row r's key takes a candidate. Nothing waits for the old key: an old row
+// whose key improved is found afterwards by its index (k_inc_rescore).
+__device__ __forceinline__ void flush_row(const IncState &s, int64_t r, unsigned long long key)
+{
+    atomicMin(&s.keys[r], key);
 }
 
 // Diagonal k = excl + thread, over the chunk's new columns [w0, w1]. All
 // threads step through the columns together (column j = w0 + t at step t); a
-// diagonal joins at its first new column with a row (j = max(k, w0)). Each
-// pair updates its row's key with its own atomic. The column's key is the
-// same for the whole grid at a step: it takes the minimum over the wave, then
-// over the block in LDS, and the block adds one global atomic per column at
-// the end.
+// diagonal joins at its first new column with a row (j = max(k, w0)).
+// Rows: lane l of a wave holds row w0 + t - k at step t, which lane l + 1
+// holds at step t + 1, so each lane keeps a running row key that moves one
+// lane up per step; the key leaving lane 63 is final for this wave and takes
+// one atomic. Columns: the column's key is the same for the whole grid at a
+// step; it takes the minimum over the wave, then over the block in LDS, and
+// the block adds one global atomic per column at the end.
 template <int KIND, int PC>
 __global__ void __launch_bounds__(INC_BLOCK) k_inc_columns(IncState s, int64_t w0, int64_t w1,
                                                            int32_t refresh)
@@ -186,28 +266,50 @@ __global__ void __launch_bounds__(INC_BLOCK) k_inc_columns(IncState s, int64_t w
             S = inc_start<KIND, PC>(s, i, js);
     }
     __syncthreads();
-    for (int64_t t = 0; t < steps; ++t) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long kr = KEY_NONE;             // key of row w0 + t - k
+    // One step (column j = w0 + t, operands o); the last step of the chunk
+    // keeps its row keys for the final flush.
+    auto walk_step = [&](int64_t t, const IncOps &o, bool last) {
         const int64_t j = w0 + t;
         const int64_t i = j - k;
         unsigned long long kc = KEY_NONE;
         if (mine && j >= js) {
-            if (j > js) S += inc_step<KIND, PC>(s, i, j);
+            if (j > js) S += inc_update<KIND, PC>(o, s.p);
             bool ok = true;
             double v = S;
             if (KIND == ACAMP) {
-                ok = !s.isconst[i] && !s.isconst[j];
-                v = fma(S * s.invn[i], -s.invn[j], 1.0);     // 1 - rho
+                ok = !o.ci && !o.cj;
+                v = fma(S * o.ni, -o.nj, 1.0);     // 1 - rho
             }
             if (ok) {
                 const unsigned long long ki = pack_key(v, (unsigned long long)j, mask);
-                const unsigned long long old = atomicMin(&s.keys[i], ki);
-                if (ki < old && i < w0) s.dirty[i] = 1;
+                kr = ki < kr ? ki : kr;
                 kc = pack_key(v, (unsigned long long)i, mask);
             }
         }
         kc = wave_min_u64(kc);
-        if ((threadIdx.x & 63) == 0 && kc != KEY_NONE) atomicMin(&colk[t], kc);
+        if (lane == 63 && kc != KEY_NONE) atomicMin(&colk[t], kc);
+        if (!last) {
+            if (lane == 63 && kr != KEY_NONE) flush_row(s, i, kr);
+            kr = shift_up_none(kr);
+        }
+    };
+    // batches of INC_BATCH steps before the last one, their operands loaded
+    // first; then the rest one by one
+    constexpr int U = INC_BATCH;
+    const int64_t full = (steps - 1) / U * U;
+    int64_t t0 = 0;
+    for (; t0 < full; t0 += U) {
+        IncOps op[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) op[u] = inc_load<KIND>(s, w0 + t0 + u - k, w0 + t0 + u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) walk_step(t0 + u, op[u], false);
     }
+    for (; t0 < steps; ++t0) walk_step(t0, inc_load<KIND>(s, w0 + t0 - k, w0 + t0), t0 + 1 == steps);
+    // the rows still held: lane l holds row w1 - k
+    if (kr != KEY_NONE) flush_row(s, w1 - k, kr);
     if (mine) s.col_new[w1 - k] = S;
     __syncthreads();
     for (int64_t t = threadIdx.x; t < steps; t += INC_BLOCK) {
@@ -216,17 +318,17 @@ __global__ void __launch_bounds__(INC_BLOCK) k_inc_columns(IncState s, int64_t w
     }
 }
 
-// Rows [0, w1]: flagged old rows and every new window take the exact FP64
-// distance of their winner.
+// Rows [0, w1]: every new window, and every old row whose key improved, take
+// the exact FP64 distance of their winner. Each pair is visited once, so an
+// old row's key improved exactly when its index is no longer the stored I.
 template <int KIND, int PC>
 __global__ void k_inc_rescore(IncState s, int64_t w0, int64_t w1)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r > w1) return;
-    if (r < w0 && !s.dirty[r]) return;
-    s.dirty[r] = 0;
     const unsigned long long key = s.keys[r];
     const unsigned long long mask = (1ull << s.gb) - 1ull;
+    if (r < w0 && (key == KEY_NONE || (int64_t)(key & mask) == s.I[r])) return;
     if (key == KEY_NONE || (KIND == ACAMP && s.isconst[r])) {
         s.P[r] = __longlong_as_double(0x7FF0000000000000ll);
         s.I[r] = -1;
@@ -257,7 +359,6 @@ __global__ void k_inc_rebuild(IncState s)
         else v = (PC == P_ONE) ? P : (PC == P_THREE ? P * P * P : pow(P, s.p));
         s.keys[r] = pack_key(v, (unsigned long long)j, mask);
     }
-    s.dirty[r] = 0;
     const int64_t w = s.N - 1;
     if (w - r >= s.excl) s.col_new[r] = inc_start<KIND, PC>(s, r, w);
 }
@@ -309,7 +410,7 @@ struct mp_inc {
     int cur = 0;                 // col[cur] holds the last column
     int64_t *I = nullptr;
     unsigned long long *keys = nullptr;
-    uint8_t *isconst = nullptr, *dirty = nullptr;
+    uint8_t *isconst = nullptr;
     std::mutex mu_lock;
 };
 
@@ -332,7 +433,6 @@ IncState view(mp_inc *h, int64_t N)
     s.mu = h->mu;
     s.invn = h->invn;
     s.isconst = h->isconst;
-    s.dirty = h->dirty;
     s.col_old = h->col[h->cur];
     s.col_new = h->col[1 - h->cur];
     s.N = N;
@@ -360,8 +460,7 @@ hipError_t dispatch(int32_t kind, int32_t pclass, F &&f)
 
 void free_inc(mp_inc *h)
 {
-    void *ptrs[] = {h->T, h->P, h->mu, h->invn, h->col[0], h->col[1], h->I, h->keys, h->isconst,
-                    h->dirty};
+    void *ptrs[] = {h->T, h->P, h->mu, h->invn, h->col[0], h->col[1], h->I, h->keys, h->isconst};
     for (void *q : ptrs) hipFree(q);
 }
 
@@ -408,7 +507,7 @@ int mp_inc_create(int32_t m, int32_t kind, double p, int32_t excl, int64_t capac
     if ((rc = inc_alloc(&h->T, capacity)) || (rc = inc_alloc(&h->P, W)) ||
         (rc = inc_alloc(&h->I, W)) || (rc = inc_alloc(&h->keys, W)) ||
         (rc = inc_alloc(&h->mu, W)) || (rc = inc_alloc(&h->invn, W)) ||
-        (rc = inc_alloc(&h->isconst, W)) || (rc = inc_alloc(&h->dirty, W)) ||
+        (rc = inc_alloc(&h->isconst, W)) ||
         (rc = inc_alloc(&h->col[0], W)) || (rc = inc_alloc(&h->col[1], W))) {
         free_inc(h);
         delete h;
