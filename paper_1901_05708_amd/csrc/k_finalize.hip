@@ -233,8 +233,15 @@ __global__ void k_pick_pivots(Batch b)
     const Fallback &fb = b.fb;
     const int32_t jb = blockIdx.x;
     if (fb.job_flag[jb] == 0) return;
-    const Series s = load_uniform(&b.jobs[jb]).s;
+    const Job J = load_uniform(&b.jobs[jb]);
+    const Series &s = J.s;
     const int lane = threadIdx.x;
+    if (J.group_ok) {
+        // a partial sweep queues only rows without an upper bound, which no
+        // pivot bound can prune: no pivots
+        if (lane < FB_PIVOTS) fb.pivots[jb * FB_PIVOTS + lane] = -1;
+        return;
+    }
     for (int k = 0; k < FB_PIVOTS; ++k) {
         const int64_t c0 = ((2 * (int64_t)k + 1) * s.N) / (2 * FB_PIVOTS);
         int64_t found = -1;
@@ -269,6 +276,7 @@ __global__ void __launch_bounds__(256) k_pivot_dist(Batch b)
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= s.N) return;
     const int32_t c = fb.pivots[jb * FB_PIVOTS + k];
+    if (c < 0) return;          // unused pivot: the scan never reads its column
     float d;
     switch (sel_of(s.kind, s.pclass)) {
     case SEL_AAMP: d = pivot_distance<AAMP, P_TWO>(s, c, j); break;
@@ -301,6 +309,19 @@ __device__ __forceinline__ void scan_unit(const Series &s, const Fallback &fb, i
     const bool staged = m <= FB_MAXM;
     {
         const int64_t i = fb.rows[r];
+        if (gok) {
+            // a partial sweep: skip a chunk with no column on the call's
+            // diagonal groups (diagonals |i - j| over the chunk's columns)
+            const int64_t c0 = c * FB_CHUNK, c1 = min(c0 + FB_CHUNK, s.N) - 1;
+            int64_t dlo = c0 > i ? c0 - i : (c1 < i ? i - c1 : 0);
+            const int64_t dhi = c0 > i ? c1 - i : (c1 < i ? i - c0 : max(i - c0, c1 - i));
+            dlo = max(dlo, (int64_t)s.excl);
+            bool any = false;
+            for (int64_t g = (dlo - s.excl) / ANY_GROUP; dlo <= dhi && g <= (dhi - s.excl) / ANY_GROUP;
+                 ++g)
+                any = any || as_global(gok)[g] != 0;
+            if (!any) return;
+        }
         const double thr = fb.ub[r] * (1.0 + 1e-9);
         const double mi = (KIND == ACAMP) ? s.mu[i] : 0.0;
         const double ni = (KIND == ACAMP) ? s.invn[i] : 1.0;
