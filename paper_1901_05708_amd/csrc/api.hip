@@ -441,24 +441,27 @@ int64_t band_rows_total(int64_t N, int64_t excl, int64_t W, int64_t *nbands)
 // amplified far beyond what the winner's self-check can see.
 constexpr int32_t FP32_MIN_M = 32;
 
-// A band sweep of a launch: a contiguous range of the job table, all in one
-// precision, with its own band-row space.
+// A band sweep of a launch: a contiguous range of the job table, all of one
+// distance specialisation and precision, with its own band-row space. Each
+// runs the kernel specialised for its distance.
 struct Group {
     int32_t first = 0, count = 0;
     int64_t rows = 0;
     int64_t rb_off = 0;        // its row_base entries (count + 1) in the table
     uint32_t sels = 0;
     int32_t grid = 0;
+    int32_t kd = 8;            // diagonals per lane
+    bool fp32 = false;
 };
 
 // A launch laid out: the job table (pointers bound to a workspace by bind())
-// ordered as [FP64 band jobs][FP32 band jobs][other jobs], the two band
-// sweeps' row_base prefixes, and the sizes of every per-launch array.
+// ordered as [band jobs by group: FP64 groups, then FP32 groups][other jobs],
+// each band sweep's row_base prefix, and the sizes of every per-launch array.
 struct Layout {
     std::vector<Job> jobs;
-    std::vector<int64_t> row_base;       // group 0 (count + 1), then group 1 (count + 1)
+    std::vector<int64_t> row_base;       // per group: count + 1 entries
     std::vector<int64_t> stream_off;     // per job (table order)
-    Group g[2];                          // 0: FP64 band sweep, 1: FP32 band sweep
+    std::vector<Group> groups;
     int64_t band_entries = 0;
     int64_t stream_total = 0, key_total = 0;
     int64_t max_N = 0, max_stream = 0, simple_diag = 0, simple_segs = 0;
@@ -503,14 +506,12 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
     if (force_fb != 1 && force_fb != 2) force_fb = 0;
     L.count = env_int("MP_COUNT_PAIRS", 0) == 1;
 
-    // p-norms with other p than 1, 2, 3 get a band kernel only in a launch
-    // of such jobs alone (their kernel holds no other distance)
-    bool all_pgen = true;
-    for (const Spec &sp : specs)
-        all_pgen = all_pgen && sel_of(sp.kind, sp.pclass) == SEL_PGEN && sp.p <= PGEN_BAND_MAX;
-    std::vector<Job> cls[3];          // FP64 band, FP32 band, other
-    std::vector<int64_t> rows_of[3];  // band rows
-    std::vector<int64_t> pos_of[3];   // positions in the row space (rows + restart costs)
+    // Classes of jobs: band jobs by precision and specialisation (index
+    // 64 fp32 + selector bits, so FP64 classes come first), then the rest.
+    constexpr int NCLS = 129, OTHER = 128;
+    std::vector<Job> cls[NCLS];
+    std::vector<int64_t> rows_of[NCLS];  // band rows
+    std::vector<int64_t> pos_of[NCLS];   // positions in the row space (rows + restart costs)
     for (const Spec &sp : specs) {
         Job j;
         std::memset(&j, 0, sizeof(j));
@@ -536,7 +537,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         const bool single =
             !partial && !sp.fcmp && want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
         const int64_t W = 64 * (single ? kd : 8);
-        const bool has_band = (sel & SEL_BAND) || (sel == SEL_PGEN && all_pgen);
+        const bool has_band = (sel & SEL_BAND) || (sel == SEL_PGEN && sp.p <= PGEN_BAND_MAX);
         bool band = has_band && ndiag >= W / 2 && choice != "simple";
         if (choice == "band" && has_band && ndiag > 0) band = true;
         if (ndiag <= 0) band = false;
@@ -571,24 +572,30 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         else
             L.pairs += pair_count(s.N, s.excl);
         L.items += nb + (band ? rows / j.seg_rows : 0);
-        const int c = band ? (s.fp32 ? 1 : 0) : 2;
+        const int c = band ? 64 * s.fp32 + (int)(sel | (s.fcmp ? SEL_FCMP : 0u)) : OTHER;
         cls[c].push_back(j);
         rows_of[c].push_back(rows);
         pos_of[c].push_back(rows + nb * (int64_t)j.band_cost);
     }
-    for (int c = 0; c < 3; ++c) {
-        if (c < 2) {
-            Group &g = L.g[c];
+    for (int c = 0; c < NCLS; ++c) {
+        if (cls[c].empty()) continue;
+        const bool grp = c != OTHER;
+        if (grp) {
+            Group g;
             g.first = (int32_t)L.jobs.size();
             g.count = (int32_t)cls[c].size();
             g.rb_off = (int64_t)L.row_base.size();
+            g.sels = (uint32_t)(c & 63);
+            g.fp32 = c >= 64;
+            g.kd = g.fp32 ? kd : 8;
+            L.groups.push_back(g);
         }
         int64_t run = 0, real = 0;
         for (size_t k = 0; k < cls[c].size(); ++k) {
             Job j = cls[c][k];
             const Series &s = j.s;
             j.row_start = run;
-            if (c < 2) L.row_base.push_back(run);
+            if (grp) L.row_base.push_back(run);
             run += pos_of[c][k];
             real += rows_of[c][k];
             j.band_base = L.band_entries;
@@ -599,20 +606,17 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
             L.stream_total += s.N + STREAM_PAD;
             L.max_N = std::max(L.max_N, s.N);
             L.max_stream = std::max(L.max_stream, s.N + STREAM_PAD);
-            if (c < 2) L.g[c].sels |= sel_of(s.kind, s.pclass) | (s.fcmp ? SEL_FCMP : 0u);
             L.jobs.push_back(j);
         }
-        if (c < 2) {
+        if (grp) {
             L.row_base.push_back(run);
-            L.g[c].rows = real;
+            L.groups.back().rows = real;
         }
     }
     L.kd = kd;
-    for (int c = 0; c < 2; ++c) {
-        Group &g = L.g[c];
-        if (!g.count || !g.rows) continue;
-        const int32_t gkd = c == 1 ? kd : 8;
-        int64_t slots = (int64_t)w.cus * band_blocks_per_cu(g.sels, gkd, c == 1);
+    for (Group &g : L.groups) {
+        if (!g.rows) continue;
+        int64_t slots = (int64_t)w.cus * band_blocks_per_cu(g.sels, g.kd, g.fp32);
         const int32_t wps = env_int("MP_WPS", 0) > 0 ? env_int("MP_WPS", 0) : tu.wps;
         if (wps > 0) slots = std::min<int64_t>(slots, (int64_t)w.cus * 4 * wps);
         // at least 64 rows per wave
@@ -680,18 +684,14 @@ Batch make_batch(const Layout &L, const Workspace &w, const Tables &t)
     return b;
 }
 
-// Diagonals per lane of a band sweep: 16 is an FP32 option only.
-int32_t group_kd(const Layout &L, int c) { return c == 1 ? L.kd : 8; }
-
 // The view of a launch that one band sweep works on.
-Batch group_view(const Batch &b, const Layout &L, int c)
+Batch group_view(const Batch &b, const Group &g)
 {
     Batch v = b;
-    const Group &g = L.g[c];
     v.jobs = b.jobs + g.first;
     v.njobs = g.count;
     v.row_base = b.row_base + g.rb_off;
-    v.band_width = 64 * group_kd(L, c);
+    v.band_width = 64 * g.kd;
     return v;
 }
 
@@ -701,14 +701,12 @@ Batch group_view(const Batch &b, const Layout &L, int c)
 // (ev[0] is recorded by the caller).
 int enqueue(const Batch &b, const Layout &L, hipStream_t st, EvSet *es)
 {
-    for (int c = 0; c < 2; ++c)
-        if (L.g[c].count) HIP_TRY(launch_plan(group_view(b, L, c), st), "plan launch");
+    for (const Group &g : L.groups) HIP_TRY(launch_plan(group_view(b, g), st), "plan launch");
     HIP_TRY(launch_prep(b, L.sels, st), "prep launch");
     if (es) HIP_TRY(hipEventRecord(es->ev[1], st), "hipEventRecord");
-    for (int c = 0; c < 2; ++c)
-        if (L.g[c].grid)
-            HIP_TRY(launch_sweep_band(group_view(b, L, c), L.g[c].sels, group_kd(L, c), c == 1,
-                                      L.g[c].grid, st),
+    for (const Group &g : L.groups)
+        if (g.grid)
+            HIP_TRY(launch_sweep_band(group_view(b, g), g.sels, g.kd, g.fp32, g.grid, st),
                     "sweep launch");
     if (L.simple_diag > 0) HIP_TRY(launch_sweep_simple(b, st), "sweep launch");
     if (es) HIP_TRY(hipEventRecord(es->ev[2], st), "hipEventRecord");
@@ -729,10 +727,15 @@ int finish_profile(EvSet &es, const Batch &b, const Layout &L, hipStream_t st)
     g_prof.pending.push_back(es);
     mp_stats &a = g_prof.acc;
     a.calls += 1;
-    a.sweep_launches += (L.g[0].grid ? 1 : 0) + (L.g[1].grid ? 1 : 0) + (L.simple_diag > 0 ? 1 : 0);
+    int32_t kd = 0;
+    for (const Group &g : L.groups) {
+        a.sweep_launches += g.grid ? 1 : 0;
+        if (g.grid) kd = std::max(kd, g.kd);
+    }
+    a.sweep_launches += L.simple_diag > 0 ? 1 : 0;
     a.pairs += L.pairs;
     a.refresh_rows = L.R_report;
-    a.diags_per_lane = L.g[1].grid ? L.kd : (L.g[0].grid ? 8 : 0);
+    a.diags_per_lane = kd;
     a.items = (int32_t)std::min<int64_t>(L.items, INT32_MAX);
     return MP_OK;
 }

@@ -165,9 +165,9 @@ __device__ __forceinline__ T load_uniform(const T *p)
 // Everything a launch works on. Band-row positions: a band sweep's work is
 // the concatenation over its jobs of each job's bands (band t of a job covers
 // diagonals [excl + t W, excl + (t+1) W) and has N - excl - t W rows). A
-// launch holds up to two band sweeps (FP64 and FP32 jobs), each over a
-// contiguous range of the job table; a sweep sees a Batch restricted to its
-// range.
+// launch holds one band sweep per distance specialisation and precision
+// among its jobs, each over a contiguous range of the job table; a sweep
+// sees a Batch restricted to its range.
 struct Batch {
     const Job *jobs;           // njobs entries
     const int64_t *row_base;   // band sweeps: njobs + 1 row_start values, then the total
@@ -212,8 +212,8 @@ constexpr uint32_t SEL_BAND = SEL_AAMP | SEL_ACAMP | SEL_P1 | SEL_P3;
 constexpr double PGEN_BAND_MAX = 6.0;
 
 // --- launch wrappers (return the hipError_t of the launch) -------------------
-// The row_base table of a one-job launch (at most 3 entries: the two band
-// sweeps' prefixes, one of them empty).
+// The row_base table of a one-job launch (at most one band sweep: its start
+// and end, 2 entries).
 struct RowBase4 {
     int64_t v[4];
     int32_t count;
