@@ -142,11 +142,12 @@ typedef struct mp_job {
 } mp_job;
 
 /*
- * mp_batch -- matrix profiles of many independent series in one persistent
- * launch of the sweep: the bands of diagonals of every series are laid end to
- * end and split evenly over the waves of one grid, whatever the mix of
- * lengths, window lengths and distances (the single-series kernels of
- * Algorithms 1-3, extended over a job table).
+ * mp_batch -- matrix profiles of many independent series in one call: for
+ * each distance (and precision) among the jobs, one persistent launch of the
+ * sweep lays the bands of diagonals of all its series end to end and splits
+ * them evenly over the waves of one grid, whatever the mix of lengths and
+ * window lengths (the single-series kernels of Algorithms 1-3, extended over
+ * a job table).
  *
  * jobs is a HOST array of njobs entries (read during the call only),
  * 0 <= njobs <= 65535. Each job obeys the single-series rules above; output
