@@ -74,7 +74,15 @@ extern "C" {
 /* Relative tolerance on profile values guaranteed by MP_FP32_REFRESH. */
 #define MP_FP32_RTOL 1e-4
 
-/* Largest supported series length (keys pack a window index in 31 bits). */
+/*
+ * Largest supported series length (keys pack a window index in 31 bits).
+ * The sweep compares candidates on packed keys whose low b = ceil(log2 N)
+ * mantissa bits hold the partner index. Two candidates whose minimised
+ * values differ by less than 2^-(52 - b) relative therefore count as tied,
+ * and the reported partner is within that of the best: 4.7e-10 for
+ * N <= 2^21, growing to 4.8e-7 at N = 2^31 (FP64). P is always the exact
+ * FP64 distance of the reported pair.
+ */
 #define MP_MAX_N ((int64_t)1 << 31)
 
 /*
