@@ -847,11 +847,14 @@ int record(hipEvent_t e, hipStream_t s)
     return MP_OK;
 }
 
-// The faster of two timed runs of a candidate (after an untimed one) on
-// stream ls; candidates within a few percent of each other otherwise swap
-// places from call to call.
+// The faster of two timed runs of a candidate (after a first, warming run)
+// on stream ls; candidates within a few percent of each other otherwise swap
+// places from call to call. A candidate whose first run already takes 1.5
+// times the best time so far (best >= 0) is not run again: its first time
+// is reported.
 int time_candidate(const std::vector<Spec> &specs, int32_t precision, const Tuning &tu,
-                   Workspace &w, hipStream_t ls, hipEvent_t e0, hipEvent_t e1, float *ms)
+                   Workspace &w, hipStream_t ls, hipEvent_t e0, hipEvent_t e1, float best,
+                   float *ms)
 {
     Layout L;
     RC_TRY(make_layout(specs, precision, tu, w, &L));
@@ -861,16 +864,21 @@ int time_candidate(const std::vector<Spec> &specs, int32_t precision, const Tuni
     int rc = upload_tables(L, &t);
     if (!rc) {
         const Batch b = make_batch(L, w, t);
-        rc = enqueue(b, L, ls, nullptr);
-        for (int rep = 0; rep < 2 && !rc; ++rep) {
-            if (!(rc = record(e0, ls)) && !(rc = enqueue(b, L, ls, nullptr)) &&
-                !(rc = record(e1, ls))) {
-                float t = 0.0f;
-                hipError_t e = hipEventSynchronize(e1);
-                if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-                if (e != hipSuccess) rc = fail_hip(e, "autotune timing");
-                else if (rep == 0 || t < *ms) *ms = t;
-            }
+        auto timed_run = [&](float *out) {
+            int r;
+            if ((r = record(e0, ls)) || (r = enqueue(b, L, ls, nullptr)) || (r = record(e1, ls)))
+                return r;
+            hipError_t e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(out, e0, e1);
+            return e == hipSuccess ? MP_OK : fail_hip(e, "autotune timing");
+        };
+        float first = 0.0f;
+        rc = timed_run(&first);
+        const bool hopeless = !rc && best >= 0.0f && first > 1.5f * best;
+        if (hopeless) *ms = first;
+        for (int rep = 0; rep < 2 && !rc && !hopeless; ++rep) {
+            float tr = 0.0f;
+            if (!(rc = timed_run(&tr)) && (rep == 0 || tr < *ms)) *ms = tr;
         }
         hipError_t es = hipStreamSynchronize(ls);
         if (!rc && es != hipSuccess) rc = fail_hip(es, "autotune");
@@ -901,7 +909,7 @@ int autotune(const std::vector<Spec> &specs, int32_t precision, Workspace &w, hi
     for (const Spec &sp : specs) m_min = std::min(m_min, sp.m);
     for (const Tuning &tu : tune_candidates(precision, m_min)) {
         float ms = 0.0f;
-        if ((rc = time_candidate(specs, precision, tu, w, ls, e0, e1, &ms))) break;
+        if ((rc = time_candidate(specs, precision, tu, w, ls, e0, e1, best_ms, &ms))) break;
         if (best_ms < 0.0f || ms < best_ms) {
             best_ms = ms;
             *best = tu;
