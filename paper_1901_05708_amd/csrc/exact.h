@@ -48,32 +48,6 @@ __device__ __forceinline__ void visit_pairs(gptr<double> a, gptr<double> b, int 
     for (int l = nb * U; l < m; ++l) f(a[l], b[l]);
 }
 
-// Calls f(w[l]) for l = 0 .. m-1 in order, U samples per block, with the next
-// block's loads issued before the current block is consumed.
-template <int U, typename Fn>
-__device__ __forceinline__ void visit_window(gptr<double> w, int m, Fn f)
-{
-    double x0[U], x1[U];
-    auto load = [&](double (&x)[U], int l) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = w[l + u];
-    };
-    auto run = [&](const double (&x)[U]) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) f(x[u]);
-    };
-    const int nb = m / U;
-    if (nb > 0) load(x0, 0);
-    for (int k = 0; k < nb; k += 2) {
-        if (k + 1 < nb) load(x1, (k + 1) * U);
-        run(x0);
-        if (k + 1 >= nb) break;
-        if (k + 2 < nb) load(x0, (k + 2) * U);
-        run(x1);
-    }
-    for (int l = nb * U; l < m; ++l) f(w[l]);
-}
-
 // One term of the exact sums: the squared difference of the z-normalized
 // samples (times 1/m), the squared difference, or |difference|^p.
 template <int KIND, int PC>

@@ -80,32 +80,50 @@ __device__ __forceinline__ Series inc_series(const IncState &s)
     return v;
 }
 
-// Window statistics of windows [w0, w1] (two passes, mean around the first
-// sample), key reset and cleared flags.
-__global__ void k_inc_stats(IncState s, int64_t w0, int64_t w1)
+constexpr int STATS_WAVES = 4;   // windows per block of k_inc_stats (one wave each)
+
+// Sum over the 64 lanes of the wave, in every lane.
+__device__ __forceinline__ double wave_sum(double x)
 {
-    const int64_t w = w0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w > w1) return;
-    s.keys[w] = KEY_NONE;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Window statistics of windows [w0, w1] (two passes, mean around the first
+// sample) and key reset. One wave per window: the lanes take every 64th
+// sample, then the wave adds their partial sums.
+__global__ void __launch_bounds__(64 * STATS_WAVES) k_inc_stats(IncState s, int64_t w0, int64_t w1)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = w0 + (int64_t)blockIdx.x * STATS_WAVES + (threadIdx.x >> 6);
+    if (w > w1) return;                          // the whole wave
+    if (lane == 0) s.keys[w] = KEY_NONE;
     if (s.kind != ACAMP) return;
     const gptr<double> x = as_global(s.T) + w;
     const int m = s.m;
     const double x0 = x[0];
     double sum = 0.0;
     bool same = true;
-    visit_window<8>(x, m, [&](double v) {
+    for (int l = lane; l < m; l += 64) {
+        const double v = x[l];
         sum += v - x0;
         same = same && (v == x0);
-    });
+    }
+    sum = wave_sum(sum);
+    const bool all_same = __ballot(!same) == 0;
     const double mu = x0 + sum / (double)m;
     double ss = 0.0;
-    visit_window<8>(x, m, [&](double v) {
-        const double d = v - mu;
+    for (int l = lane; l < m; l += 64) {
+        const double d = x[l] - mu;
         ss = fma(d, d, ss);
-    });
-    s.mu[w] = mu;
-    s.isconst[w] = same ? 1 : 0;
-    s.invn[w] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) {
+        s.mu[w] = mu;
+        s.isconst[w] = all_same ? 1 : 0;
+        s.invn[w] = (all_same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
+    }
 }
 
 // The quantity the recurrence carries along a diagonal, directly: the
@@ -368,7 +386,8 @@ static hipError_t launch_chunk(const IncState &s, int64_t w0, int64_t w1, bool r
                                hipStream_t st)
 {
     const int B = 256;
-    hipLaunchKernelGGL(k_inc_stats, dim3((unsigned)((w1 - w0 + B) / B)), dim3(B), 0, st, s, w0, w1);
+    hipLaunchKernelGGL(k_inc_stats, dim3((unsigned)((w1 - w0 + STATS_WAVES) / STATS_WAVES)),
+                       dim3(64 * STATS_WAVES), 0, st, s, w0, w1);
     if (w1 >= s.excl) {
         const int64_t nd = w1 - s.excl + 1;
         if (w1 - w0 + 1 > INC_COLS) return hipErrorInvalidValue;
@@ -386,8 +405,8 @@ static hipError_t launch_rebuild(const IncState &s, hipStream_t st)
 {
     const int B = 256;
     if (s.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_inc_stats, dim3((unsigned)((s.N + B - 1) / B)), dim3(B), 0, st, s,
-                       (int64_t)0, s.N - 1);
+    hipLaunchKernelGGL(k_inc_stats, dim3((unsigned)((s.N + STATS_WAVES - 1) / STATS_WAVES)),
+                       dim3(64 * STATS_WAVES), 0, st, s, (int64_t)0, s.N - 1);
     hipLaunchKernelGGL((k_inc_rebuild<KIND, PC>), dim3((unsigned)((s.N + B - 1) / B)), dim3(B), 0,
                        st, s);
     return hipGetLastError();
