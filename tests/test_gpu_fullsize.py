@@ -138,3 +138,24 @@ def test_ecg_fp32_sampled(mp):
     N = len(T) - m + 1
     rows = list(W.sample_rows(N, 48, seed=7)) + [max(0, c - m // 2) for c in anomalies]
     _sampled(mp, "acamp", T, m, rows, precision="fp32", label="ecg-fp32")
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("MP_FULL_ORACLE"),
+                    reason="about 6 minutes of host CPU: set MP_FULL_ORACLE=1 to run")
+@pytest.mark.timeout(1200)
+def test_rw128k_acamp_every_row(mp):
+    """The bench workload, every one of its 130817 rows against the oracle's
+    brute force (about 4.4e12 FMA on the host), in FP64 and FP32 + refresh."""
+    T, m, _ = W.rw128k()
+    excl = W.excl_default(m)
+    N = len(T) - m + 1
+    gpu = {prec: _gpu(mp, "acamp", T, m, precision=prec) for prec in ("fp64", "fp32")}
+    step = 8192
+    for lo in range(0, N, step):
+        rows = np.arange(lo, min(lo + step, N), dtype=np.int64)
+        Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=excl, rows=rows)
+        for prec, (P, I) in gpu.items():
+            check_profile(T, m, "acamp", 2.0, excl, P[rows], I[rows], Pr, Ir, Qr,
+                          1e-9 if prec == "fp64" else 1e-4, 1e-6, rows=rows,
+                          label=f"rw128k-all-{prec}-{lo}")
+        _note(f"rw128k every row: rows {lo}..{rows[-1]} of {N} match in both precisions")
