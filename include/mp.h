@@ -30,7 +30,9 @@
  *    MP_FP32_REFRESH runs the bulk of the recurrence in single precision,
  *    restarted from an exact FP64 value every R rows, with FP64 window
  *    statistics and FP64 rescoring of every winner; rows it cannot certify
- *    within MP_FP32_RTOL are recomputed in FP64.
+ *    within MP_FP32_RTOL are recomputed in FP64. It applies to ACAMP and
+ *    p = 1 with m >= 32; AAMP, other p-norms and shorter windows run the
+ *    FP64 sweep under MP_FP32_REFRESH.
  *  - R is the refresh interval (rows between exact FP64 restarts of the
  *    recurrence). R = 0 lets the library choose: the first call with a given
  *    series shape (n, m, distance, excl, precision) times a few candidate
@@ -100,9 +102,9 @@ int mp_aamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precisi
  * Distance: DP_{i,j} = (sum_{l<m} |t_{i+l} - t_{j+l}|^p)^(1/p)  (Def. 2.6, Eq. 2,
  * read with an absolute value), real p >= 1; updated with Lemma 2. p = 2 gives
  * exactly the result of mp_aamp. p must be finite and >= 1. p = 1 and 3 have
- * fast paths; other p up to 6 evaluate pow per term in the band sweep (FP64,
- * also under MP_FP32_REFRESH); larger p, and other p inside a batch holding
- * other distances, run on a slower one-thread-per-diagonal sweep.
+ * fast paths; other p up to 6 evaluate pow per term in the band sweep; larger
+ * p run on a slower one-thread-per-diagonal sweep. Only p = 1 has an FP32
+ * sweep: every other p runs in FP64 under MP_FP32_REFRESH too.
  */
 int mp_pnorm(const double *T, int64_t n, int32_t m, double p, int32_t excl,
              int32_t precision, int32_t R, double *P, int64_t *I, void *stream);

@@ -441,6 +441,16 @@ int64_t band_rows_total(int64_t N, int64_t excl, int64_t W, int64_t *nbands)
 // amplified far beyond what the winner's self-check can see.
 constexpr int32_t FP32_MIN_M = 32;
 
+// Distances with an FP32 sweep: ACAMP and p = 1. The certification checks
+// the winner's FP32 drift only. The AAMP and p = 3 sums cancel large
+// increments against small best-match sums, so a row's true best candidate
+// can drift by more than its winner and lose unseen. Every-row checks against
+// the oracle found one row 2.79e-4 above its minimum in the 131072-sample
+// walk (AAMP), and one 1.004e-4 above in the sines p = 3 workload (also with
+// a tighter check). ACAMP keys 1 - rho next to 1, and the walk's every row
+// met 1e-4. Other distances run the FP64 sweep under MP_FP32_REFRESH.
+constexpr uint32_t SEL_FP32 = SEL_ACAMP | SEL_P1;
+
 // A band sweep of a launch: a contiguous range of the job table, all of one
 // distance specialisation and precision, with its own band-row space. Each
 // runs the kernel specialised for its distance.
@@ -535,7 +545,7 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         // the sweep this job would join decides its band width
         s.fcmp = sp.fcmp;
         const bool single =
-            !partial && !sp.fcmp && want32 && s.m >= FP32_MIN_M && (sel & SEL_BAND);
+            !partial && !sp.fcmp && want32 && s.m >= FP32_MIN_M && (sel & SEL_FP32);
         const int64_t W = 64 * (single ? kd : 8);
         const bool has_band = (sel & SEL_BAND) || (sel == SEL_PGEN && sp.p <= PGEN_BAND_MAX);
         bool band = has_band && ndiag >= W / 2 && choice != "simple";

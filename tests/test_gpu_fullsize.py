@@ -159,3 +159,67 @@ def test_rw128k_acamp_every_row(mp):
                           1e-9 if prec == "fp64" else 1e-4, 1e-6, rows=rows,
                           label=f"rw128k-all-{prec}-{lo}")
         _note(f"rw128k every row: rows {lo}..{rows[-1]} of {N} match in both precisions")
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("MP_FULL_ORACLE"),
+                    reason="about 6 minutes of host CPU: set MP_FULL_ORACLE=1 to run")
+@pytest.mark.timeout(1200)
+def test_sines_p3_every_row(mp):
+    """The sines workload with p = 3 (the p-norm whose FP32 sweep queues the
+    most rows), every one of its 262017 rows against the oracle's brute force,
+    in FP64 and FP32 + refresh."""
+    T, m = W.sines()
+    excl = W.excl_default(m)
+    N = len(T) - m + 1
+    gpu = {prec: _gpu(mp, "pnorm", T, m, p=3.0, precision=prec) for prec in ("fp64", "fp32")}
+    step = 16384
+    for lo in range(0, N, step):
+        rows = np.arange(lo, min(lo + step, N), dtype=np.int64)
+        Pr, Ir, Qr = oracle.profile(T, m, "pnorm", p=3.0, excl=excl, rows=rows)
+        for prec, (P, I) in gpu.items():
+            check_profile(T, m, "pnorm", 3.0, excl, P[rows], I[rows], Pr, Ir, Qr,
+                          1e-9 if prec == "fp64" else 1e-4, 0.0, rows=rows,
+                          label=f"sines-p3-all-{prec}-{lo}")
+        _note(f"sines p=3 every row: rows {lo}..{rows[-1]} of {N} match in both precisions")
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("MP_FULL_ORACLE"),
+                    reason="about 5 minutes of host CPU: set MP_FULL_ORACLE=1 to run")
+@pytest.mark.timeout(1200)
+def test_rw128k_aamp_every_row(mp):
+    """The headline series under the pure Euclidean distance, every row
+    against the oracle, in FP64 and FP32 + refresh."""
+    T, m, _ = W.rw128k()
+    excl = W.excl_default(m)
+    N = len(T) - m + 1
+    gpu = {prec: _gpu(mp, "aamp", T, m, precision=prec) for prec in ("fp64", "fp32")}
+    step = 8192
+    for lo in range(0, N, step):
+        rows = np.arange(lo, min(lo + step, N), dtype=np.int64)
+        Pr, Ir, Qr = oracle.profile(T, m, "aamp", excl=excl, rows=rows)
+        for prec, (P, I) in gpu.items():
+            check_profile(T, m, "aamp", 2.0, excl, P[rows], I[rows], Pr, Ir, Qr,
+                          1e-9 if prec == "fp64" else 1e-4, 0.0, rows=rows,
+                          label=f"rw128k-aamp-all-{prec}-{lo}")
+        _note(f"rw128k aamp every row: rows {lo}..{rows[-1]} of {N} match in both precisions")
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("MP_FULL_ORACLE"),
+                    reason="about 6 minutes of host CPU: set MP_FULL_ORACLE=1 to run")
+@pytest.mark.timeout(1200)
+def test_sines_p1_every_row(mp):
+    """The sines workload with p = 1, every one of its 262017 rows against the
+    oracle's brute force, in FP64 and FP32 + refresh."""
+    T, m = W.sines()
+    excl = W.excl_default(m)
+    N = len(T) - m + 1
+    gpu = {prec: _gpu(mp, "pnorm", T, m, p=1.0, precision=prec) for prec in ("fp64", "fp32")}
+    step = 16384
+    for lo in range(0, N, step):
+        rows = np.arange(lo, min(lo + step, N), dtype=np.int64)
+        Pr, Ir, Qr = oracle.profile(T, m, "pnorm", p=1.0, excl=excl, rows=rows)
+        for prec, (P, I) in gpu.items():
+            check_profile(T, m, "pnorm", 1.0, excl, P[rows], I[rows], Pr, Ir, Qr,
+                          1e-9 if prec == "fp64" else 1e-4, 0.0, rows=rows,
+                          label=f"sines-p1-all-{prec}-{lo}")
+        _note(f"sines p=1 every row: rows {lo}..{rows[-1]} of {N} match in both precisions")
