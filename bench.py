@@ -161,7 +161,7 @@ def headline(args, mp, W, torch):
     Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     res = {"T": T, "m": m, "excl": excl, "pairs": pairs, "n": n}
-    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32",)):
+    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32", "fp32_auto")):
         out = {}
 
         def step():
@@ -192,6 +192,7 @@ def headline(args, mp, W, torch):
             "refresh_rows": prof["refresh_rows"],
             "diags_per_lane": prof["diags_per_lane"],
             "items": prof["items"],
+            "fp32_jobs": prof["fp32_jobs"],
             "wall_s": wall,
             "P": out["PI"][0].cpu().numpy(),
             "I": out["PI"][1].cpu().numpy(),
@@ -258,7 +259,7 @@ def batch_workload(args, mp, W, torch):
     pairs = sum(mp.pair_count(jb.n, jb.m, mp.default_excl(jb.m)) for jb in jobs)
     stream = torch.cuda.current_stream()
     res = {"jobs": len(jobs), "pairs": pairs, "samples": int(total_n)}
-    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32",)):
+    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32", "fp32_auto")):
         P = torch.empty(total_out, dtype=torch.float64, device="cuda")
         I = torch.empty(total_out, dtype=torch.int64, device="cuda")
         mp.set_profiling(False)       # clears autotune time and replay counters
@@ -289,11 +290,14 @@ def batch_workload(args, mp, W, torch):
             "refresh_rows": prof["refresh_rows"],
             "diags_per_lane": prof["diags_per_lane"],
             "fallback_rows_per_step": prof["fallback_rows"],
+            "band_jobs": prof["band_jobs"],
+            "fp32_jobs": prof["fp32_jobs"],
             "phases_ms": {"prep": round(prof["ms_prep"], 3), "sweep": round(prof["ms_sweep"], 3),
                           "finalize": round(prof["ms_finalize"], 3)},
         }
     if "fp32" in res:
         res["fp32_gain"] = round(res["fp32"]["value"] / res["fp64"]["value"], 4)
+        res["fp32_auto_gain"] = round(res["fp32_auto"]["value"] / res["fp64"]["value"], 4)
     res["workload"] = ("512 series (seed 4): random walk or noisy sine, n ~ U{2048..65536}, "
                        "m in {32,64,128,256}, AAMP/ACAMP 50/50, excl = ceil(m/4); one mp_batch "
                        "call per step, graph replay")
@@ -484,6 +488,18 @@ def main():
                                    "sweep": round(f32["sweep_ms"], 4),
                                    "finalize": round(f32["finalize_ms"], 4)},
             "sweep_gain_vs_fp64": round(f64["sweep_ms"] / f32["sweep_ms"], 4),
+        }
+    if "fp32_auto" in h:
+        fa = h["fp32_auto"]
+        out["fp32_auto"] = {
+            "value": round(fa["value"], 3),
+            "ms_per_step": round(fa["ms_per_step"], 4),
+            "autotune_ms": round(fa["autotune_ms"], 1),
+            "gain_vs_fp64": round(fa["value"] / f64["value"], 4),
+            "rtol": 1e-4,
+            "sweep": "fp32" if fa["fp32_jobs"] else "fp64",
+            "refresh_rows": fa["refresh_rows"],
+            "fallback_rows_per_step": fa["fallback_rows"],
         }
     # motif / discord extraction on the headline profile (k = 10 each)
     Pd = torch.as_tensor(f64["P"], device="cuda")

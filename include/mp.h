@@ -33,6 +33,12 @@
  *    within MP_FP32_RTOL are recomputed in FP64. It applies to ACAMP and
  *    p = 1 with m >= 32; AAMP, other p-norms and shorter windows run the
  *    FP64 sweep under MP_FP32_REFRESH.
+ *    MP_FP32_AUTO keeps the MP_FP32_RTOL contract but lets the autotuner
+ *    (R = 0) time the FP64 sweep beside the FP32 candidates and keep the
+ *    faster per shape: near good matches the FP32 sweep's exact search of
+ *    uncertified rows can cost more than it saves. With an explicit R (or
+ *    MP_AUTOTUNE=0) it behaves as MP_FP32_REFRESH. mp_stats.fp32_jobs
+ *    reports which sweep ran.
  *  - R is the refresh interval (rows between exact FP64 restarts of the
  *    recurrence). R = 0 lets the library choose: the first call with a given
  *    series shape (n, m, distance, excl, precision) times a few candidate
@@ -68,12 +74,14 @@ extern "C" {
 
 #define MP_FP64 0
 #define MP_FP32_REFRESH 1
+#define MP_FP32_AUTO 2
 
 #define MP_KIND_AAMP 0  /* pure Euclidean                                      */
 #define MP_KIND_PNORM 1 /* p-norm                                              */
 #define MP_KIND_ACAMP 2 /* z-normalized Euclidean                              */
 
-/* Relative tolerance on profile values guaranteed by MP_FP32_REFRESH. */
+/* Relative tolerance on profile values guaranteed by MP_FP32_REFRESH and
+ * MP_FP32_AUTO. */
 #define MP_FP32_RTOL 1e-4
 
 /*
@@ -320,6 +328,8 @@ typedef struct mp_stats {
     int32_t graph_replays;   /* mp_batch calls served by replaying a captured graph,
                                 since the last mp_set_profiling() (counted whether
                                 or not profiling is on)                          */
+    int32_t band_jobs;       /* jobs swept by the band kernel, most recent call  */
+    int32_t fp32_jobs;       /* of those, jobs swept in FP32, most recent call   */
 } mp_stats;
 
 void mp_set_profiling(int on);

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MP_LIBRARY") or os.path.join(_HERE, "libmp.so")
 
 MP_OK, MP_EINVAL, MP_ENOMEM, MP_EHIP, MP_EUNSUPPORTED = 0, -1, -2, -3, -4
-MP_FP64, MP_FP32_REFRESH = 0, 1
+MP_FP64, MP_FP32_REFRESH, MP_FP32_AUTO = 0, 1, 2
 KIND_AAMP, KIND_PNORM, KIND_ACAMP = 0, 1, 2
 FP32_RTOL = 1e-4
 
@@ -55,7 +55,8 @@ class MpStats(ctypes.Structure):
                 ("pairs_visited", ctypes.c_int64),
                 ("calls", ctypes.c_int32), ("sweep_launches", ctypes.c_int32),
                 ("refresh_rows", ctypes.c_int32), ("diags_per_lane", ctypes.c_int32),
-                ("items", ctypes.c_int32), ("graph_replays", ctypes.c_int32)]
+                ("items", ctypes.c_int32), ("graph_replays", ctypes.c_int32),
+                ("band_jobs", ctypes.c_int32), ("fp32_jobs", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -122,6 +123,8 @@ def _prec(precision) -> int:
         return MP_FP64
     if precision in ("fp32", "fp32_refresh", MP_FP32_REFRESH):
         return MP_FP32_REFRESH
+    if precision in ("fp32_auto", MP_FP32_AUTO):
+        return MP_FP32_AUTO
     raise ValueError(f"unknown precision {precision!r}")
 
 

@@ -372,8 +372,8 @@ int make_spec(const double *T, int64_t n, int32_t m, int32_t kind, double p, int
 
 int check_precision(int32_t precision)
 {
-    if (precision != MP_FP64 && precision != MP_FP32_REFRESH)
-        return fail(MP_EINVAL, "precision must be MP_FP64 or MP_FP32_REFRESH");
+    if (precision != MP_FP64 && precision != MP_FP32_REFRESH && precision != MP_FP32_AUTO)
+        return fail(MP_EINVAL, "precision must be MP_FP64, MP_FP32_REFRESH or MP_FP32_AUTO");
     return MP_OK;
 }
 
@@ -386,6 +386,9 @@ struct Tuning {
     int32_t R = 0;
     int32_t grid_mult = 1;
     int32_t wps = 0;
+    // MP_FP32_AUTO only: sweep every job in FP64, which meets the FP32
+    // tolerance; chosen when it times faster than every FP32 candidate
+    bool sweep64 = false;
 };
 
 // Longest FP64 refresh interval per window length. A step's rounding error is
@@ -479,6 +482,7 @@ struct Layout {
     int32_t kd = 8;
     int64_t pairs = 0, items = 0;
     int32_t R_report = 0;
+    int32_t band_jobs = 0, fp32_jobs = 0;
     bool count = false;                  // pair-visit counting (test mode)
     // Whether a row can reach the exact search: an ACAMP job (a constant
     // partner can win the sweep), an FP32 sweep (its self-check) or the test
@@ -504,7 +508,8 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
                 const Workspace &w, Layout *out)
 {
     Layout L;
-    const bool want32 = precision == MP_FP32_REFRESH;
+    const bool want32 =
+        precision == MP_FP32_REFRESH || (precision == MP_FP32_AUTO && !tu.sweep64);
     const char *sw = std::getenv("MP_SWEEP");
     const std::string choice = sw ? sw : "auto";
     // diagonals per lane of the FP32 sweep; the FP64 sweep always uses 8
@@ -562,6 +567,8 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
             rows = band_rows_total(s.N, s.excl, W, &nb);
         }
         if (band) {
+            L.band_jobs += 1;
+            L.fp32_jobs += s.fp32;
             j.band_cost = band_cost(sel, s.m);
             int64_t R = sp.R > 0 ? sp.R
                                  : (tu.R > 0 && s.fp32 == want32 ? tu.R : default_R(sel, s.fp32, s.m));
@@ -747,6 +754,8 @@ int finish_profile(EvSet &es, const Batch &b, const Layout &L, hipStream_t st)
     a.refresh_rows = L.R_report;
     a.diags_per_lane = kd;
     a.items = (int32_t)std::min<int64_t>(L.items, INT32_MAX);
+    a.band_jobs = L.band_jobs;
+    a.fp32_jobs = L.fp32_jobs;
     return MP_OK;
 }
 
@@ -833,20 +842,22 @@ int upload_tables(const Layout &L, Tables *t)
 // fits the register file in FP32) times refresh interval. In FP64 the interval
 // stays within FP64_R_PER_M times the shortest window of the launch; long
 // windows also try grids of one or two waves per SIMD, since every wave pays
-// at least one O(m) restart.
+// at least one O(m) restart. MP_FP32_AUTO tries the FP32 and the FP64 shapes.
 std::vector<Tuning> tune_candidates(int32_t precision, int32_t m_min)
 {
     std::vector<Tuning> c;
-    if (precision == MP_FP32_REFRESH) {
+    if (precision != MP_FP64) {
         for (int kd : {8, 16})
             for (int R : {256, 512, 1024, 2048}) c.push_back(Tuning{kd, R, 1, 0});
-    } else {
-        for (int R : {1024, 2048, 4096}) c.push_back(Tuning{8, R, 1, 0});
+    }
+    if (precision != MP_FP32_REFRESH) {
+        const bool sweep64 = precision == MP_FP32_AUTO;
+        for (int R : {1024, 2048, 4096}) c.push_back(Tuning{8, R, 1, 0, sweep64});
         const int64_t rmax = std::min<int64_t>(FP64_R_PER_M * m_min, 1 << 24);
-        if (rmax / 2 > 4096) c.push_back(Tuning{8, (int32_t)(rmax / 2), 1, 0});
-        if (rmax > 4096) c.push_back(Tuning{8, (int32_t)rmax, 1, 0});
+        if (rmax / 2 > 4096) c.push_back(Tuning{8, (int32_t)(rmax / 2), 1, 0, sweep64});
+        if (rmax > 4096) c.push_back(Tuning{8, (int32_t)rmax, 1, 0, sweep64});
         if (m_min >= 2048)
-            for (int wps : {1, 2}) c.push_back(Tuning{8, (int32_t)rmax, 1, wps});
+            for (int wps : {1, 2}) c.push_back(Tuning{8, (int32_t)rmax, 1, wps, sweep64});
     }
     return c;
 }

@@ -51,6 +51,7 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.mp_acamp(dummy, 1 << 31, 4, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
     # bad precision / R
     assert lib.mp_aamp(dummy, 100, 10, 0, 7, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_aamp(dummy, 100, 10, 0, 3, 0, dummy, dummy, None) == mp.MP_EINVAL
     assert lib.mp_aamp(dummy, 100, 10, 0, 0, -1, dummy, dummy, None) == mp.MP_EINVAL
     # bad p
     assert lib.mp_pnorm(dummy, 100, 10, 0.5, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
@@ -133,6 +134,16 @@ def test_incremental_arguments_rejected_without_gpu(lib):
     assert lib.mp_inc_append(None, ctypes.c_void_p(16), 10, None) == mp.MP_EINVAL
     assert lib.mp_inc_read(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == mp.MP_EINVAL
     lib.mp_inc_destroy(None)                       # a no-op
+
+
+def test_precision_constants_match_header():
+    src = open(os.path.join(ROOT, "include", "mp.h")).read()
+    for name in ("MP_FP64", "MP_FP32_REFRESH", "MP_FP32_AUTO"):
+        got = re.search(r"#define %s (\d+)" % name, src)
+        assert got and int(got.group(1)) == getattr(mp, name), name
+    assert mp._prec("fp32_auto") == mp.MP_FP32_AUTO
+    with pytest.raises(ValueError):
+        mp._prec("fp16")
 
 
 def test_strerror_never_null(lib):
