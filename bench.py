@@ -5,17 +5,19 @@ Headline workload (one step = one full call of the hot path: window
 statistics and difference streams, the diagonal sweep, FP64 rescoring,
 certification and exact search): z-normalized profile (ACAMP) of a random
 walk of n = 131072 samples with 20 constant runs and 10 planted motif pairs,
-m = 256, exclusion |i - j| < m/4. Timed in FP64 (``value``) and in
-FP32 + FP64 refresh (``fp32_refresh``), with the gain between them.
+m = 256, exclusion |i - j| < m/4. Timed in FP64 (``value``), in
+FP32 + FP64 refresh (``fp32_refresh``) and in MP_FP32_AUTO (``fp32_auto``: the
+same tolerance, the faster sweep), with the gains over FP64.
 
 Batch workload (``batch``): 512 random-walk / noisy-sine series of length
 U{2048..65536}, m in {32, 64, 128, 256}, AAMP / ACAMP mixed, one mp_batch call
-per step (autotuned, captured once, then replayed as a HIP graph), in both
-precisions.
+per step (autotuned, captured once, then replayed as a HIP graph), in the
+same three precision modes.
 
 Inputs are resident in HBM before timing starts. Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-cpu]
+                    [--no-fp32] [--no-auto]
 """
 from __future__ import annotations
 
@@ -52,7 +54,9 @@ def parse():
     ap.add_argument("--configs", action="store_true",
                     help="also time the other single-series workloads (rw8k, sines p = 1 and 3, "
                          "ecg ACAMP and AAMP) in both precisions; adds a minute or two")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 + refresh runs")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32 + refresh and MP_FP32_AUTO runs")
+    ap.add_argument("--no-auto", action="store_true", help="skip the MP_FP32_AUTO runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: auto)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -153,6 +157,12 @@ def timed(fn, steps, warmup, stream):
     return ev[0].elapsed_time(ev[steps]) / steps, statistics.median(per)
 
 
+def _lower_precisions(args):
+    if args.no_fp32:
+        return ()
+    return ("fp32",) if args.no_auto else ("fp32", "fp32_auto")
+
+
 def headline(args, mp, W, torch):
     T, m, planted = W.rw128k()
     n = len(T)
@@ -161,7 +171,7 @@ def headline(args, mp, W, torch):
     Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     res = {"T": T, "m": m, "excl": excl, "pairs": pairs, "n": n}
-    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32", "fp32_auto")):
+    for prec in ("fp64",) + _lower_precisions(args):
         out = {}
 
         def step():
@@ -259,7 +269,7 @@ def batch_workload(args, mp, W, torch):
     pairs = sum(mp.pair_count(jb.n, jb.m, mp.default_excl(jb.m)) for jb in jobs)
     stream = torch.cuda.current_stream()
     res = {"jobs": len(jobs), "pairs": pairs, "samples": int(total_n)}
-    for prec in ("fp64",) + (() if args.no_fp32 else ("fp32", "fp32_auto")):
+    for prec in ("fp64",) + _lower_precisions(args):
         P = torch.empty(total_out, dtype=torch.float64, device="cuda")
         I = torch.empty(total_out, dtype=torch.int64, device="cuda")
         mp.set_profiling(False)       # clears autotune time and replay counters
@@ -297,6 +307,7 @@ def batch_workload(args, mp, W, torch):
         }
     if "fp32" in res:
         res["fp32_gain"] = round(res["fp32"]["value"] / res["fp64"]["value"], 4)
+    if "fp32_auto" in res:
         res["fp32_auto_gain"] = round(res["fp32_auto"]["value"] / res["fp64"]["value"], 4)
     res["workload"] = ("512 series (seed 4): random walk or noisy sine, n ~ U{2048..65536}, "
                        "m in {32,64,128,256}, AAMP/ACAMP 50/50, excl = ceil(m/4); one mp_batch "
