@@ -37,17 +37,17 @@ def _walk_with_motif(n, m, seed):
     return T
 
 
-def _series(mp, kind, T, m, p, precision):
+def _series(mp, kind, T, m, p, precision, R=0):
     import torch
     Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
     excl = W.excl_default(m)
     mp.set_profiling(True)
     if kind == "aamp":
-        P, I = mp.aamp(Td, m, excl=excl, precision=precision)
+        P, I = mp.aamp(Td, m, excl=excl, precision=precision, R=R)
     elif kind == "pnorm":
-        P, I = mp.pnorm(Td, m, p=p, excl=excl, precision=precision)
+        P, I = mp.pnorm(Td, m, p=p, excl=excl, precision=precision, R=R)
     else:
-        P, I = mp.acamp(Td, m, excl=excl, precision=precision)
+        P, I = mp.acamp(Td, m, excl=excl, precision=precision, R=R)
     torch.cuda.synchronize()
     st = mp.profile_read()
     mp.set_profiling(False)
@@ -84,6 +84,20 @@ def test_stats_report_the_sweep_precision(mp, kind, p, expect32):
     assert (st64["band_jobs"], st64["fp32_jobs"]) == (1, 0)
     _, _, st32 = _series(mp, kind, T, 64, p, "fp32")
     assert (st32["band_jobs"], st32["fp32_jobs"]) == (1, expect32)
+
+
+@pytest.mark.parametrize("kind,p", [("acamp", 2.0), ("pnorm", 1.0)])
+def test_auto_with_explicit_interval_runs_the_fp32_sweep(mp, kind, p):
+    # no tuning with an explicit R: the mode then behaves as MP_FP32_REFRESH
+    m, R = 64, 512
+    T = _walk_with_motif(5000, m, 21)
+    excl = W.excl_default(m)
+    _note(f"fp32_auto explicit R={R} {kind} p={p}")
+    P, I, st = _series(mp, kind, T, m, p, "fp32_auto", R=R)
+    assert (st["band_jobs"], st["fp32_jobs"], st["refresh_rows"]) == (1, 1, R)
+    Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl)
+    atol = 1e-6 if kind == "acamp" else 0.0
+    check_profile(T, m, kind, p, excl, P, I, Pr, Ir, Qr, 1e-4, atol, label=f"auto-R-{kind}")
 
 
 def test_auto_batch_within_fp32_tolerance(mp):
