@@ -143,6 +143,32 @@ int mp_acamp_fcmp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t R
                   int64_t *I, void *stream);
 
 /*
+ * mp_profile_noalloc -- mp_aamp / mp_pnorm / mp_acamp (selected by kind,
+ * MP_KIND_*; p is read for MP_KIND_PNORM only) for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. It calls no hipMalloc, hipFree or other
+ * allocating routine. Every array the pipeline needs lives in one static
+ * device array of 40 MiB per GPU, held from the library's load until the
+ * process ends; its address is looked up on the first call on each device.
+ *
+ * Arguments, layout and results are those of the single-series entry points,
+ * with three differences:
+ *  - the series may have at most MP_NOALLOC_MAX_N windows (n - m + 1);
+ *    longer series return MP_EINVAL before anything is enqueued;
+ *  - R = 0 takes the library's default refresh interval instead of running
+ *    the autotuner (MP_FP32_AUTO then behaves as MP_FP32_REFRESH);
+ *  - profiling (mp_set_profiling) records nothing for these calls.
+ * All calls on one GPU share its array and leave their contents there; each
+ * call clears what it needs cleared. Two calls on one GPU whose kernels can
+ * run at the same time (on different streams with no ordering between them)
+ * race; calls serialized on one stream do not.
+ */
+#define MP_NOALLOC_MAX_N ((int64_t)1 << 18)
+int mp_profile_noalloc(int32_t kind, const double *T, int64_t n, int32_t m, double p,
+                       int32_t excl, int32_t precision, int32_t R, double *P, int64_t *I,
+                       void *stream);
+
+/*
  * One series of a batch. Offsets are in elements. Series b occupies
  * T_cat[t_off .. t_off + n) and its N_b = n - m + 1 outputs go to
  * P_cat[out_off ..), I_cat[out_off ..); I values are local to the series.

@@ -27,13 +27,14 @@ MP_FP64, MP_FP32_REFRESH, MP_FP32_AUTO = 0, 1, 2
 KIND_AAMP, KIND_PNORM, KIND_ACAMP = 0, 1, 2
 FP32_RTOL = 1e-4
 
-EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_acamp_fcmp", "mp_batch", "mp_topk",
-            "mp_anytime",
+EXPORTED = ("mp_aamp", "mp_pnorm", "mp_acamp", "mp_acamp_fcmp", "mp_profile_noalloc", "mp_batch",
+            "mp_topk", "mp_anytime",
             "mp_anytime_groups", "mp_anytime_order", "mp_inc_create", "mp_inc_append",
             "mp_inc_state", "mp_inc_read", "mp_inc_destroy", "mp_strerror", "mp_release",
             "mp_set_profiling", "mp_profile_read")
 ANYTIME_GROUP = 512
 MP_MOTIFS, MP_DISCORDS = 0, 1
+NOALLOC_MAX_N = 1 << 18
 
 
 class MpError(RuntimeError):
@@ -80,6 +81,8 @@ def load(path: str = LIB_PATH):
     lib.mp_acamp.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp]
     lib.mp_acamp_fcmp.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
     lib.mp_acamp_fcmp.restype = ctypes.c_int
+    lib.mp_profile_noalloc.argtypes = [i32, vp, i64, i32, dbl, i32, i32, i32, vp, vp, vp]
+    lib.mp_profile_noalloc.restype = ctypes.c_int
     lib.mp_batch.argtypes = [vp, ctypes.POINTER(MpJob), i32, i32, vp, vp, vp]
     for f in (lib.mp_aamp, lib.mp_pnorm, lib.mp_acamp, lib.mp_batch):
         f.restype = ctypes.c_int
@@ -188,6 +191,41 @@ def acamp(T, m: int, excl: Optional[int] = None, precision="fp64", R: int = 0, s
     _check(load().mp_acamp(T.data_ptr(), n, m, excl or 0, _prec(precision), R,
                            P.data_ptr(), I.data_ptr(), _stream(stream)))
     return P, I
+
+
+def profile_noalloc(T, m: int, kind: str = "aamp", p: float = 2.0, excl: Optional[int] = None,
+                    precision="fp64", R: int = 0, P=None, I=None, stream=None,
+                    validate: bool = True):
+    """mp_aamp / mp_pnorm / mp_acamp without device allocation inside the
+    library (mp_profile_noalloc): at most NOALLOC_MAX_N windows, R = 0 takes
+    the default interval (no autotuning). P, I may be preallocated outputs
+    (contiguous float64 / int64 tensors of N entries). Returns (P, I)."""
+    import torch
+    T, n, N, P0, I0 = _series(T, m, validate) if P is None else _series_noout(T, m, validate)
+    if P is None:
+        P, I = P0, I0
+    elif (I is None or P.dtype != torch.float64 or I.dtype != torch.int64 or P.numel() != N
+          or I.numel() != N or not P.is_contiguous() or not I.is_contiguous()):
+        raise TypeError("P, I must be contiguous float64 / int64 tensors of N entries")
+    _check(load().mp_profile_noalloc(_KIND_OF[kind], T.data_ptr(), n, int(m), float(p),
+                                     int(excl or 0), _prec(precision), R, P.data_ptr(),
+                                     I.data_ptr(), _stream(stream)))
+    return P, I
+
+
+def _series_noout(T, m: int, validate: bool):
+    import torch
+    if not isinstance(T, torch.Tensor) or T.device.type != "cuda":
+        raise TypeError("T must be a torch tensor on a HIP (cuda) device")
+    if T.dtype != torch.float64 or T.dim() != 1:
+        raise TypeError("T must be a 1-D float64 tensor")
+    T = T.contiguous()
+    if validate:
+        _check_values(T)
+    n = T.shape[0]
+    if not (1 <= m <= n):
+        raise ValueError("need 1 <= m <= len(T)")
+    return T, n, n - m + 1, None, None
 
 
 def acamp_fcmp(T, m: int, excl: Optional[int] = None, R: int = 0, stream=None,

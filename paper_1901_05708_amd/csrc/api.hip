@@ -1216,6 +1216,161 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
     return MP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// single series without device allocation (mp_profile_noalloc): every array
+// of the pipeline is a slice of one static device array
+// ---------------------------------------------------------------------------
+// Largest window count of mp_profile_noalloc and the size of its array. Per
+// window the pipeline needs three FP64 and three FP32 stream entries (plus
+// STREAM_PAD per series), the window statistics, the key, the exact-search
+// queue entry and FB_PIVOTS pivot distances: 149 bytes, 39.2 MB at the limit.
+constexpr int64_t NOALLOC_MAX_N = MP_NOALLOC_MAX_N;
+constexpr size_t NOALLOC_BYTES = (size_t)40 << 20;
+constexpr size_t NOALLOC_ALIGN = 256;
+
+// Sub-allocator over the array: slices of at least NOALLOC_ALIGN bytes, in
+// call order. With base == 0 it only adds up the bytes a layout needs.
+struct Carver {
+    uintptr_t base = 0;
+    size_t used = 0;
+    template <class T>
+    T *take(int64_t count)
+    {
+        const size_t bytes = ((size_t)std::max<int64_t>(count, 1) * sizeof(T) + NOALLOC_ALIGN - 1) &
+                             ~(NOALLOC_ALIGN - 1);
+        T *p = base ? (T *)(base + used) : nullptr;
+        used += bytes;
+        return p;
+    }
+};
+
+// The workspace and tables of a one-job layout as slices of the array.
+void carve(Carver &c, const Layout &L, Workspace *w, Tables *t)
+{
+    const int64_t S = L.stream_total, K = L.key_total;
+    w->x = c.take<double>(S);
+    w->y = c.take<double>(S);
+    w->z = c.take<double>(S);
+    w->xf = c.take<float>(S);
+    w->yf = c.take<float>(S);
+    w->zf = c.take<float>(S);
+    w->mu = c.take<double>(K);
+    w->invn = c.take<double>(K);
+    w->isconst = c.take<uint8_t>(K);
+    w->keys = c.take<unsigned long long>(K);
+    w->fb_rows = c.take<int32_t>(K);
+    w->fb_job = c.take<int32_t>(K);
+    w->fb_keys = c.take<unsigned long long>(K);
+    w->fb_ub = c.take<double>(K);
+    w->fb_pd = c.take<float>(K * FB_PIVOTS);
+    w->counters = c.take<int32_t>(64);
+    w->visits = c.take<unsigned long long>(1);
+    w->stream_cap = S;
+    w->key_cap = K;
+    t->jobs = c.take<Job>(1);
+    t->row_base = c.take<int64_t>(4);
+    t->band = c.take<int64_t>(L.band_entries);
+    t->flags = c.take<int32_t>(1);
+    t->pivots = c.take<int32_t>(FB_PIVOTS);
+}
+
+// Bytes carve() takes at the window limit: the largest layout is one job of
+// NOALLOC_MAX_N windows swept in bands of 512 diagonals (at most
+// NOALLOC_MAX_N / 512 + 1 bands, one more band-table entry).
+constexpr size_t noalloc_bytes_at_limit()
+{
+    constexpr size_t A = NOALLOC_ALIGN;
+    constexpr size_t S = (size_t)(NOALLOC_MAX_N + STREAM_PAD), K = (size_t)NOALLOC_MAX_N;
+    constexpr size_t per_array = A;   // rounding slack of each slice
+    return 3 * (8 * S) + 3 * (4 * S) + K * (8 + 8 + 1 + 8 + 4 + 4 + 8 + 8 + 4 * FB_PIVOTS) +
+           64 * 4 + 8 + sizeof(Job) + 4 * 8 + (K / 512 + 2) * 8 + 4 + FB_PIVOTS * 4 +
+           25 * per_array;
+}
+static_assert(noalloc_bytes_at_limit() <= NOALLOC_BYTES,
+              "the static array holds a series of MP_NOALLOC_MAX_N windows");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+// Per device: the device address of `scratch` (the array's name is a host
+// stand-in, not a device address), looked up on the first call on the device
+// with it current, and the architecture facts of the planner.
+constexpr int NOALLOC_DEVICES = 64;
+struct NoallocDevice {
+    void *ptr;
+    int ready;   // 0: not looked up, 1: gfx950 and ptr valid, -1: not a gfx950 GPU
+    int cus;
+};
+NoallocDevice g_noalloc[NOALLOC_DEVICES];
+
+int noalloc_device(NoallocDevice **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_DEVICES)
+        return fail(MP_EUNSUPPORTED, "device ordinal beyond the allocation-free entry's table");
+    NoallocDevice &d = g_noalloc[dev];
+    if (d.ready == 0) {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            d.ready = -1;
+        } else {
+            void *p = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+            if (!p) return fail(MP_EHIP, "hipGetSymbolAddress(scratch) returned no address");
+            d.ptr = p;
+            d.cus = prop.multiProcessorCount;
+            d.ready = 1;
+        }
+    }
+    if (d.ready < 0) return fail(MP_EUNSUPPORTED, "the current HIP device is not a gfx950 GPU");
+    *out = &d;
+    return MP_OK;
+}
+
+int run_noalloc(int32_t kind, const double *T, int64_t n, int32_t m, double p, int32_t excl,
+                int32_t precision, int32_t R, double *P, int64_t *I, void *stream)
+{
+    Spec sp;
+    RC_TRY(make_spec(T, n, m, kind, p, excl, R, P, I, &sp));
+    RC_TRY(check_precision(precision));
+    if (n - m + 1 > NOALLOC_MAX_N)
+        return fail(MP_EINVAL, "n - m + 1 exceeds MP_NOALLOC_MAX_N windows");
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    NoallocDevice *d = nullptr;
+    RC_TRY(noalloc_device(&d));
+    hipStream_t st = (hipStream_t)stream;
+
+    // no trial runs: R = 0 takes the per-distance default interval
+    Workspace w;
+    w.cus = d->cus;
+    w.arch_ok = 1;
+    Layout L;
+    RC_TRY(make_layout({sp}, precision, Tuning(), w, &L));
+    Tables t;
+    Carver size_only;
+    carve(size_only, L, &w, &t);
+    if (size_only.used > NOALLOC_BYTES)
+        return fail(MP_EINVAL, "the series needs more than the allocation-free array holds");
+    Carver c;
+    c.base = (uintptr_t)d->ptr;
+    carve(c, L, &w, &t);
+    bind(L, w);
+    const Batch b = make_batch(L, w, t);
+    RowBase4 rb;
+    std::memset(&rb, 0, sizeof(rb));
+    rb.count = (int32_t)L.row_base.size();
+    for (int32_t k = 0; k < rb.count && k < 4; ++k) rb.v[k] = L.row_base[k];
+    HIP_TRY(launch_store_job(L.jobs[0], rb, t.jobs, t.row_base, st), "job table");
+    RC_TRY(enqueue(b, L, st, nullptr));
+    g_last_code = MP_OK;
+    return MP_OK;
+}
+
 }  // namespace
 
 // Hooks for the other host files of the library (incremental profiles).
@@ -1254,6 +1409,13 @@ int mp_acamp_fcmp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t R
                   int64_t *I, void *stream)
 {
     return run_series(T, n, m, ACAMP, 2.0, excl, MP_FP64, R, P, I, stream, 1);
+}
+
+int mp_profile_noalloc(int32_t kind, const double *T, int64_t n, int32_t m, double p,
+                       int32_t excl, int32_t precision, int32_t R, double *P, int64_t *I,
+                       void *stream)
+{
+    return run_noalloc(kind, T, n, m, p, excl, precision, R, P, I, stream);
 }
 
 int mp_anytime(int32_t kind, const double *T, int64_t n, int32_t m, double p, int32_t excl,

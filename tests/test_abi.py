@@ -63,6 +63,15 @@ def test_invalid_arguments_rejected_without_gpu(lib):
     assert lib.mp_acamp_fcmp(dummy, 100, 10, 0, -1, dummy, dummy, None) == mp.MP_EINVAL
     msg = lib.mp_strerror(mp.MP_EINVAL).decode()
     assert "invalid argument" in msg
+    # the allocation-free variant: the same rules, plus its window limit
+    lim = mp.NOALLOC_MAX_N
+    assert lib.mp_profile_noalloc(0, None, 100, 10, 2.0, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_profile_noalloc(3, dummy, 100, 10, 2.0, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_profile_noalloc(1, dummy, 100, 10, 0.5, 0, 0, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_profile_noalloc(2, dummy, 100, 10, 2.0, 0, 5, 0, dummy, dummy, None) == mp.MP_EINVAL
+    assert lib.mp_profile_noalloc(0, dummy, lim + 64, 64, 2.0, 0, 0, 0, dummy, dummy,
+                                  None) == mp.MP_EINVAL
+    assert "MP_NOALLOC_MAX_N" in lib.mp_strerror(mp.MP_EINVAL).decode()
     # batch: bad job table
     jobs = (mp.MpJob * 1)()
     jobs[0] = mp.MpJob(0, 100, 0, 10, 9, 0, 0, 2.0)
