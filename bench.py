@@ -395,7 +395,7 @@ def anytime_curve(mp, h, torch):
 
 def fcmp_variant(args, mp, h, torch):
     """The headline series with the sweep comparing pairs on the F of
-    Sec. 4.3 (mp_acamp_fcmp), timed like the headline at the refresh interval
+    Sec. 4.4 (mp_acamp_fcmp), timed like the headline at the refresh interval
     the headline run chose, against the headline's own FP64 figures (pairs
     compared on rho): ms per call, sweep ms, and index agreement."""
     Td = torch.as_tensor(h["T"], device="cuda")

@@ -53,9 +53,11 @@
  *    No C++ exception crosses the ABI. mp_strerror() describes the last error
  *    of the calling thread.
  *  - Ownership of internal state: the library keeps a grow-only device
- *    workspace per device, and for mp_batch a cache of captured HIP graphs;
- *    mp_release() frees both. Calls on one device must not overlap in time
- *    (they share the workspace); serialize them on one stream.
+ *    workspace per device and caller stream (keyed by the hipStream_t value),
+ *    and for mp_batch a cache of captured HIP graphs; mp_release() frees
+ *    both. Calls on different streams use different workspaces and may run
+ *    concurrently; calls on one stream are ordered by it. Host-side, the
+ *    library serialises its calls with one lock, so any thread may call.
  */
 #ifndef MP_H
 #define MP_H
@@ -106,7 +108,7 @@ int mp_aamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precisi
             int32_t R, double *P, int64_t *I, void *stream);
 
 /*
- * mp_pnorm -- p-norm matrix profile (AAMP extended to L^p, Sec. 3.3).
+ * mp_pnorm -- p-norm matrix profile (AAMP extended to L^p, Sec. 3.4).
  * Distance: DP_{i,j} = (sum_{l<m} |t_{i+l} - t_{j+l}|^p)^(1/p)  (Def. 2.6, Eq. 2,
  * read with an absolute value), real p >= 1; updated with Lemma 2. p = 2 gives
  * exactly the result of mp_aamp. p must be finite and >= 1. p = 1 and 3 have
@@ -129,7 +131,7 @@ int mp_acamp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t precis
 
 /*
  * mp_acamp_fcmp -- mp_acamp in FP64 with the sweep comparing pairs on the
- * quantity F of Sec. 4.3 (Eq. 9) instead of rho. For two windows,
+ * quantity F of Sec. 4.4 (Eq. 9) instead of rho. For two windows,
  * F = -m^2 rho |rho|: F grows exactly when DZ does, and
  * DZ^2 = 2m + 2 sign(F) sqrt|F| (Eq. 10, read as the squared distance). The
  * band sweep keys each pair on 1 + F / m^2 = 1 - rho |rho|, one multiply more
@@ -250,7 +252,7 @@ int mp_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pre
  *   Rows are rescored exactly in FP64 as in the full profile; P[i] is the
  *   distance of (i, I[i]). Errors: MP_EINVAL for a bad group index, ngroups
  *   < 0, resume not 0 or 1, p > 6, or the single-series argument errors.
- *   Stream-ordered and asynchronous; uses the device workspace.
+ *   Stream-ordered and asynchronous; uses the workspace of its stream.
  */
 #define MP_ANYTIME_GROUP 512
 int mp_anytime_groups(int64_t n, int32_t m, int32_t excl, int64_t *ngroups);
@@ -275,7 +277,7 @@ int mp_anytime(int32_t kind, const double *T, int64_t n, int32_t m, double p, in
  * candidate (fewer than k once every finite window is excluded; entries past
  * it are left untouched). excl >= 1 (typically the profile's exclusion zone
  * or m); 0 <= k <= 65536; 0 <= N < MP_MAX_N. Stream-ordered and
- * asynchronous; 3 small launches per round; uses the device workspace.
+ * asynchronous; 3 small launches per round; uses the workspace of its stream.
  */
 #define MP_MOTIFS 0
 #define MP_DISCORDS 1
@@ -322,7 +324,7 @@ void mp_inc_destroy(mp_inc *h);
  * library and valid until the next call on the same thread. */
 const char *mp_strerror(int code);
 
-/* Free the device workspace and graph cache of every device. Safe to call at
+/* Free the workspaces and graph cache of every device and stream. Safe to call at
  * any time no call is in flight; later calls re-allocate. */
 void mp_release(void);
 

@@ -17,7 +17,7 @@
  *                 0-indexed here, the paper is 1-indexed)
  *   Euclidean     D_{i,j} = sqrt(sum_l (t_{i+l}-t_{j+l})^2)        (Def. 2.5, Eq. 1)
  *   p-norm        DP_{i,j} = (sum_l |t_{i+l}-t_{j+l}|^p)^(1/p)     (Def. 2.6, Eq. 2;
- *                 read with an absolute value, real p >= 1, as in Sec. 3.3)
+ *                 read with an absolute value, real p >= 1, as in Sec. 3.4)
  *   z-normalized  DZ_{i,j} = sqrt(sum_l ((t_{i+l}-mu_i)/s_i - (t_{j+l}-mu_j)/s_j)^2)
  *                 (Def. 2.7, Eq. 3), mu and s the window mean and population
  *                 standard deviation (App. A). A window whose samples are all

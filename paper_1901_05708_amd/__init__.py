@@ -231,7 +231,7 @@ def _series_noout(T, m: int, validate: bool):
 def acamp_fcmp(T, m: int, excl: Optional[int] = None, R: int = 0, stream=None,
                validate: bool = True):
     """z-normalized matrix profile with the sweep comparing pairs on the F
-    of Sec. 4.3 instead of rho (mp_acamp_fcmp; FP64). Returns (P, I)."""
+    of Sec. 4.4 instead of rho (mp_acamp_fcmp; FP64). Returns (P, I)."""
     T, n, N, P, I = _series(T, m, validate)
     _check(load().mp_acamp_fcmp(T.data_ptr(), n, m, excl or 0, R, P.data_ptr(), I.data_ptr(),
                                 _stream(stream)))

@@ -56,10 +56,13 @@ int fail_hip(hipError_t e, const char *where)
 std::recursive_mutex g_mu;
 
 // ---------------------------------------------------------------------------
-// per-device workspace (grow-only): the per-window arrays of every series of
-// a launch, concatenated
+// workspaces (grow-only), one per device and caller stream: the per-window
+// arrays of every series of a launch, concatenated. Calls on different
+// streams never share one, so they may run concurrently.
 // ---------------------------------------------------------------------------
 struct Workspace {
+    int dev = 0;
+    hipStream_t owner = nullptr;       // the caller stream it serves
     int64_t stream_cap = 0;            // stream entries (sum over jobs of N + STREAM_PAD)
     int64_t key_cap = 0;               // windows (sum over jobs of N)
     double *x = nullptr, *y = nullptr, *z = nullptr;
@@ -95,7 +98,8 @@ struct Workspace {
     double *any_P = nullptr;
     int64_t *any_I = nullptr;
     int64_t any_row_cap = 0;
-    uint64_t generation = 1;           // bumped whenever the arrays above move
+    uint64_t generation = 0;           // unique over all workspaces; renewed whenever
+                                       // the arrays above move
     int arch_ok = -1;                  // -1 unknown, 0 no, 1 gfx950
     int cus = 0;
     // library stream and fork / join events of graph launches
@@ -103,7 +107,15 @@ struct Workspace {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
-std::vector<Workspace> g_ws;
+std::list<Workspace> g_ws;           // stable addresses: graph entries point at them
+uint64_t g_generation = 0;
+
+// Per device: is it a gfx950, and its compute-unit count.
+struct DevInfo {
+    int arch_ok = -1;                  // -1 unknown, 0 no, 1 gfx950
+    int cus = 0;
+};
+std::vector<DevInfo> g_dev;
 
 void free_arrays(Workspace &w)
 {
@@ -116,7 +128,7 @@ void free_arrays(Workspace &w)
     w.keys = w.fb_keys = nullptr;
     w.fb_rows = w.fb_job = w.counters = nullptr;
     w.stream_cap = w.key_cap = 0;
-    w.generation++;
+    w.generation = ++g_generation;
 }
 
 void free_ws(Workspace &w)
@@ -150,6 +162,7 @@ int grow(T **p, size_t count, const char *what)
 {
     hipFree(*p);
     *p = nullptr;
+    if (alloc_fail_hook()) return fail(MP_ENOMEM, what);
     hipError_t e = hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
         (void)hipGetLastError();
@@ -159,19 +172,37 @@ int grow(T **p, size_t count, const char *what)
     return MP_OK;
 }
 
-int get_ws(Workspace **out, int *dev_out)
+// The workspace of the current device and the caller's stream (created on
+// first use).
+int get_ws(hipStream_t st, Workspace **out, int *dev_out)
 {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-    Workspace &w = g_ws[dev];
-    if (w.arch_ok < 0) {
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    DevInfo &di = g_dev[dev];
+    if (di.arch_ok < 0) {
         hipDeviceProp_t prop;
         HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
-        w.arch_ok = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 0;
-        w.cus = prop.multiProcessorCount;
+        di.arch_ok = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 0;
+        di.cus = prop.multiProcessorCount;
     }
-    if (!w.arch_ok) return fail(MP_EUNSUPPORTED, "the current HIP device is not a gfx950 GPU");
+    if (!di.arch_ok) return fail(MP_EUNSUPPORTED, "the current HIP device is not a gfx950 GPU");
+    Workspace *wp = nullptr;
+    for (Workspace &x : g_ws)
+        if (x.dev == dev && x.owner == st) {
+            wp = &x;
+            break;
+        }
+    if (!wp) {
+        g_ws.emplace_back();
+        wp = &g_ws.back();
+        wp->dev = dev;
+        wp->owner = st;
+        wp->arch_ok = 1;
+        wp->cus = di.cus;
+        wp->generation = ++g_generation;
+    }
+    Workspace &w = *wp;
     if (!w.job1) {
         RC_TRY(grow(&w.job1, 1, "workspace job table"));
         RC_TRY(grow(&w.row_base1, 4, "workspace job table"));
@@ -341,7 +372,7 @@ struct Spec {
     // for a whole profile
     const int32_t *groups = nullptr;
     int64_t ngroups = -1;
-    int32_t fcmp = 0;          // ACAMP compared on F (Sec. 4.3), FP64 band sweep
+    int32_t fcmp = 0;          // ACAMP compared on F (Sec. 4.4), FP64 band sweep
 };
 
 int make_spec(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
@@ -359,7 +390,7 @@ int make_spec(const double *T, int64_t n, int32_t m, int32_t kind, double p, int
     s.T = T;
     s.n = n;
     s.m = m;
-    s.kind = (kind == PNORM && p == 2.0) ? AAMP : kind;   // Sec. 3.3: p = 2 is Euclid
+    s.kind = (kind == PNORM && p == 2.0) ? AAMP : kind;   // Sec. 3.4: p = 2 is Euclid
     s.p = s.kind == PNORM ? p : 2.0;
     s.pclass = s.kind == PNORM ? pclass_of(p) : P_TWO;
     s.excl = excl > 0 ? excl : (m + 3) / 4;
@@ -778,6 +809,7 @@ struct GraphEntry {
     const double *P = nullptr;
     const int64_t *I = nullptr;
     uint64_t generation = 0;
+    const Workspace *ws = nullptr;   // the workspace its pointers point into
     Layout L;
     Tables t;
     hipGraph_t graph = nullptr;
@@ -975,10 +1007,10 @@ int run_series(const double *T, int64_t n, int32_t m, int32_t kind, double p, in
     RC_TRY(check_precision(precision));
     sp.fcmp = fcmp;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t st = (hipStream_t)stream;
     Workspace *w = nullptr;
     int dev = 0;
-    RC_TRY(get_ws(&w, &dev));
-    hipStream_t st = (hipStream_t)stream;
+    RC_TRY(get_ws(st, &w, &dev));
 
     // R = 0: the refresh interval (and, in FP32, the band width) is tuned per
     // series shape on first use
@@ -1046,10 +1078,10 @@ int run_anytime(int32_t kind, const double *T, int64_t n, int32_t m, double p, i
     sp.ngroups = ngroups;
 
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t st = (hipStream_t)stream;
     Workspace *w = nullptr;
     int dev = 0;
-    RC_TRY(get_ws(&w, &dev));
-    hipStream_t st = (hipStream_t)stream;
+    RC_TRY(get_ws(st, &w, &dev));
     Layout L;
     RC_TRY(make_layout({sp}, MP_FP64, Tuning(), *w, &L));
     RC_TRY(ensure_arrays(*w, L.stream_total, L.key_total));
@@ -1131,10 +1163,10 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
     }
 
     std::lock_guard<std::recursive_mutex> lk(g_mu);
+    hipStream_t st = (hipStream_t)stream;
     Workspace *w = nullptr;
     int dev = 0;
-    RC_TRY(get_ws(&w, &dev));
-    hipStream_t st = (hipStream_t)stream;
+    RC_TRY(get_ws(st, &w, &dev));
     RC_TRY(ensure_lib_stream(*w));
     const bool use_graph =
         !g_prof.on && env_int("MP_GRAPH", 1) != 0 && env_int("MP_COUNT_PAIRS", 0) != 1;
@@ -1145,7 +1177,7 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
         if (it->dev == dev && it->precision == precision && it->T == T_cat && it->P == P_cat &&
             it->I == I_cat && same_table(it->table, jobs, njobs))
             break;
-    if (it != g_graphs.end() && it->generation != w->generation) {
+    if (it != g_graphs.end() && (it->ws != w || it->generation != w->generation)) {
         free_entry(*it);
         g_graphs.erase(it);
         it = g_graphs.end();
@@ -1169,6 +1201,7 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
             return rc;
         }
         e.generation = w->generation;
+        e.ws = w;
         g_graphs.push_front(std::move(e));
         it = g_graphs.begin();
         while (g_graphs.size() > GRAPH_CACHE) {
@@ -1479,7 +1512,7 @@ int mp_topk(const double *P, const int64_t *I, int64_t N, int32_t k, int32_t exc
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     Workspace *w = nullptr;
     int dev = 0;
-    RC_TRY(get_ws(&w, &dev));
+    RC_TRY(get_ws((hipStream_t)stream, &w, &dev));
     if (w->topk_mask_cap < std::max<int64_t>(N, 1)) {
         RC_TRY(grow(&w->topk_mask, (size_t)std::max<int64_t>(N, 1), "top-k mask"));
         w->topk_mask_cap = std::max<int64_t>(N, 1);
@@ -1518,7 +1551,7 @@ void mp_release(void)
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);
-    for (size_t d = 0; d < g_ws.size(); ++d) {
+    for (size_t d = 0; d < g_dev.size(); ++d) {
         (void)hipSetDevice((int)d);
         (void)hipDeviceSynchronize();
         for (auto it = g_graphs.begin(); it != g_graphs.end();) {
@@ -1529,7 +1562,14 @@ void mp_release(void)
                 ++it;
             }
         }
-        free_ws(g_ws[d]);
+        for (auto it = g_ws.begin(); it != g_ws.end();) {
+            if (it->dev == (int)d) {
+                free_ws(*it);
+                it = g_ws.erase(it);
+            } else {
+                ++it;
+            }
+        }
     }
     (void)hipSetDevice(cur);
 }

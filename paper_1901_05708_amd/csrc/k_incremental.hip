@@ -486,6 +486,7 @@ void free_inc(mp_inc *h)
 template <class T>
 int inc_alloc(T **p, int64_t count)
 {
+    if (alloc_fail_hook()) return report_error(MP_ENOMEM, "incremental profile buffers");
     hipError_t e = hipMalloc((void **)p, (size_t)std::max<int64_t>(count, 1) * sizeof(T));
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
         (void)hipGetLastError();

@@ -1,5 +1,5 @@
 // k_prep.hip -- per-window preparation that sits outside the sweep's inner
-// loop: the O(m (n - m)) part of the method (Secs. 3.4 and 4.3), computed once
+// loop: the O(m (n - m)) part of the method (Secs. 3.3 and 4.3), computed once
 // per window in FP64 instead of once per diagonal.
 #include "keys.h"
 #include "mp_internal.h"

@@ -236,7 +236,7 @@ constexpr int stage_doubles()
 // computed.
 // ACAMP key of a pair from its centred cross sum S, invn_i (ri) and -invn_j
 // (cj). With q = S ri cj = -rho the default key is 1 - rho. The comparator
-// of Sec. 4.3, F = -m^2 rho |rho|, orders pairs as the distance does; its key
+// of Sec. 4.4, F = -m^2 rho |rho|, orders pairs as the distance does; its key
 // 1 + F / m^2 = 1 - rho |rho| = fma(q, |q|, 1) costs one multiply more.
 template <int PC, typename F>
 __device__ __forceinline__ F acamp_key(F S, F ri, F cj)

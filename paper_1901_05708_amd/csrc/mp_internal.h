@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace mpk {
 
@@ -15,7 +16,7 @@ enum Kind : int32_t { AAMP = 0, PNORM = 1, ACAMP = 2 };
 // have closed-form power terms, any other p goes through pow().
 enum PClass : int32_t { P_GENERIC = 0, P_ONE = 1, P_TWO = 2, P_THREE = 3 };
 // Template value of the band kernel only (never a job's pclass): its ACAMP
-// pairs are keyed on the comparator F of Sec. 4.3 instead of 1 - rho.
+// pairs are keyed on the comparator F of Sec. 4.4 instead of 1 - rho.
 constexpr int P_FCMP = 4;
 
 // Extra stream entries past N so that sweeps may read a little beyond the last
@@ -48,7 +49,7 @@ struct Series {
     int32_t excl;
     double p;
     int32_t gb;            // index bits of a global key
-    int32_t fcmp;          // ACAMP: the band sweep compares pairs on F (Sec. 4.3)
+    int32_t fcmp;          // ACAMP: the band sweep compares pairs on F (Sec. 4.4)
     // Difference streams, N + STREAM_PAD entries each.
     //   AAMP:  x = u_j = t[j+m-1] - t[j-1],  y = v_j = t[j+m-1] + t[j-1]
     //   PNORM: x = a_j = t[j+m-1],           y = b_j = t[j-1]
@@ -246,6 +247,15 @@ int report_hip(hipError_t e, const char *where);
 void report_ok();
 int profile_once(const double *T, int64_t n, int32_t m, int32_t kind, double p, int32_t excl,
                  int32_t R, double *P, int64_t *I, hipStream_t st);
+
+// Test hook of the allocation error path: with MP_FAIL_ALLOC=1 in the
+// environment every device allocation of the library fails as if the device
+// were out of memory (MP_ENOMEM), before any HIP call is made for it.
+inline bool alloc_fail_hook()
+{
+    const char *e = std::getenv("MP_FAIL_ALLOC");
+    return e && e[0] == '1' && e[1] == 0;
+}
 
 // Band-kernel facts for the planner: resident waves per CU for a selector set,
 // and the selector sets that have their own kernel (others use the mixed one).

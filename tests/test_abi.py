@@ -228,3 +228,48 @@ def test_anytime_groups_and_order_on_host(lib):
         o, _ = mp.anytime_order(200000, 64, 0, seed=100 + s)
         first[o[: o.size // 2]] += 1
     assert 0.35 < first.mean() / 200 < 0.65 and first.min() > 50 and first.max() < 150
+
+
+def _gpu_visible():
+    """Whether a GPU device node exists (checked without initialising HIP)."""
+    return os.path.exists("/dev/kfd")
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="the no-device error path needs a host without a GPU")
+def test_hip_error_without_gpu(lib):
+    """Valid arguments on a host without a GPU: the first HIP call fails and
+    the call returns MP_EHIP with the HIP error text, never crashing."""
+    dummy = ctypes.c_void_p(16)
+    rc = lib.mp_aamp(dummy, 100, 10, 0, 0, 0, dummy, dummy, None)
+    assert rc == mp.MP_EHIP
+    msg = lib.mp_strerror(rc).decode()
+    assert msg.startswith("HIP runtime error") and "hipGetDevice" in msg
+    rc = lib.mp_profile_noalloc(2, dummy, 100, 10, 2.0, 0, 0, 0, dummy, dummy, None)
+    assert rc == mp.MP_EHIP
+    jobs = (mp.MpJob * 1)(mp.MpJob(0, 100, 0, 10, mp.KIND_AAMP, 0, 0, 2.0))
+    assert lib.mp_batch(dummy, jobs, 1, 0, dummy, dummy, None) == mp.MP_EHIP
+    h = ctypes.c_void_p()
+    assert lib.mp_inc_create(16, mp.KIND_ACAMP, 2.0, 0, 1000, 0, ctypes.byref(h)) == mp.MP_EHIP
+    assert h.value is None
+
+
+def test_allocation_failure_hook(lib, monkeypatch):
+    """MP_FAIL_ALLOC=1 makes every device allocation fail as out-of-memory:
+    MP_ENOMEM, no handle returned, and the next call without the hook works
+    as before (here: reaches the device query again)."""
+    monkeypatch.setenv("MP_FAIL_ALLOC", "1")
+    h = ctypes.c_void_p()
+    rc = lib.mp_inc_create(16, mp.KIND_ACAMP, 2.0, 0, 1000, 0, ctypes.byref(h))
+    assert rc == mp.MP_ENOMEM and h.value is None
+    assert "incremental profile buffers" in lib.mp_strerror(rc).decode()
+    monkeypatch.delenv("MP_FAIL_ALLOC")
+    if not _gpu_visible():
+        rc = lib.mp_inc_create(16, mp.KIND_ACAMP, 2.0, 0, 1000, 0, ctypes.byref(h))
+        assert rc == mp.MP_EHIP and h.value is None
+
+
+def test_every_error_code_has_a_message(lib):
+    for code, word in ((mp.MP_OK, "success"), (mp.MP_EINVAL, "invalid argument"),
+                       (mp.MP_ENOMEM, "allocation failed"), (mp.MP_EHIP, "HIP runtime error"),
+                       (mp.MP_EUNSUPPORTED, "unsupported device"), (-99, "unknown error code")):
+        assert word in lib.mp_strerror(code).decode()

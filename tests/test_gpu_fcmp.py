@@ -1,5 +1,5 @@
 """GPU parity of mp_acamp_fcmp: the z-normalized profile with the band sweep
-comparing pairs on the F of Sec. 4.3 (Eq. 9). F orders pairs as the distance
+comparing pairs on the F of Sec. 4.4 (Eq. 9). F orders pairs as the distance
 does, so the profile equals the oracle's (1e-9 relative, 1e-6 absolute;
 ties allowed) and agrees with mp_acamp wherever both pick the same index."""
 import sys

@@ -4,7 +4,7 @@ Each test ties the oracle to something the paper or the mathematics fixes:
 hand-derived worked examples (tests/golden), library routines (scipy cdist,
 numpy corrcoef / mean / std), exact integer and rational brute force, the
 paper's own incremental recurrences (Lemmas 1-3), the alternative comparator
-identity of Sec. 4.3, invariants and special cases.
+identity of Sec. 4.4, invariants and special cases.
 """
 import math
 import os
@@ -191,7 +191,7 @@ def test_scipy_cdist_euclid_and_pnorm(oracle_mod, seed):
     _check_against(P, I, Q, *_lib_profile(cdist(W, W, "cityblock"), excl, lambda x: x), 1e-11)
     P, I, Q = oracle_mod.profile(T, m, "pnorm", p=3.0, excl=excl)
     _check_against(P, I, Q, *_lib_profile(cdist(W, W, "minkowski", p=3.0), excl, lambda x: x), 1e-10)
-    # p = 2 is the Euclidean special case (Sec. 3.3)
+    # p = 2 is the Euclidean special case (Sec. 3.4)
     P, I, Q = oracle_mod.profile(T, m, "pnorm", p=2.0, excl=excl)
     _check_against(P, I, Q, *_lib_profile(cdist(W, W, "euclidean"), excl, lambda x: x), 1e-11)
     P, I, Q = oracle_mod.profile(T, m, "pnorm", p=2.5, excl=excl)
@@ -319,7 +319,7 @@ def test_exact_rational_znorm(oracle_mod):
 
 def _diagonal_sweep(T, m, excl, kind, p=2.0):
     """Diagonal-wise incremental profile written from Lemmas 1-3 and the
-    description of AAMP / ACAMP (Secs. 3.2, 3.3, 4.2): for each diagonal
+    description of AAMP / ACAMP (Secs. 3.2, 3.4, 4.2): for each diagonal
     k = j - i the first pair is summed directly, every later pair on the
     diagonal is updated in O(1), and each pair updates both its row and its
     column. ACAMP uses the five running sums of Sec. 4.1."""
@@ -375,7 +375,7 @@ def test_incremental_recurrences_match(oracle_mod, kind, p):
 
 
 def test_alternative_comparator_identity(oracle_mod):
-    """Sec. 4.3: with F built from the five sums (its denominator's B_j read as
+    """Sec. 4.4: with F built from the five sums (its denominator's B_j read as
     B_j^2), 2m + 2 sign(F) sqrt|F| equals the squared z-normalized distance."""
     rng = np.random.default_rng(41)
     T = np.cumsum(rng.standard_normal(200))
