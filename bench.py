@@ -14,10 +14,21 @@ U{2048..65536}, m in {32, 64, 128, 256}, AAMP / ACAMP mixed, one mp_batch call
 per step (autotuned, captured once, then replayed as a HIP graph), in the
 same three precision modes.
 
+The other workloads (``configs``): the 8192-sample random walk (AAMP), the
+262144-sample sines (p = 1 and p = 3) and the 2,097,152-sample ECG-like series
+(ACAMP and AAMP), each in FP64 and FP32 + refresh. Long windows
+(``long_windows``, the paper's Fig. 4 shape): n = 2^18 uniform values,
+m = 256 .. 65536, AAMP and ACAMP, both precisions.
+
+Every sweep figure carries its VALU roofline fraction: algorithmic lane
+operations (the O(1) update plus one row and one column minimum per pair)
+over the sweep phase's time, measured with the library's HIP events on the
+calling stream, against 256 CUs x 64 lanes x 2.4 GHz.
+
 Inputs are resident in HBM before timing starts. Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-cpu]
-                    [--no-fp32] [--no-auto]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only LIST] [--no-batch]
+                    [--no-configs] [--no-long] [--no-cpu] [--no-fp32] [--no-auto]
 """
 from __future__ import annotations
 
@@ -37,8 +48,25 @@ METRIC = "subsequence-pair distances/s (G pairs/s) FP32+refresh vs FP64, at stat
 # VALU issue rate of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # lane-operations per second (FP64 FMA, add, mul and min are all full rate).
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# algorithmic lane-operations per pair (O(1) update + row min + column min)
-OPS_PER_PAIR = {"aamp": 5, "acamp": 6, "pnorm1": 6, "pnorm3": 8}
+# algorithmic lane-operations per pair (O(1) update + row min + column min):
+# AAMP 2 sub + 2 FMA + 2 min (the update is (u_i - u_j)(v_i - v_j) + S, one
+# FMA, but the count follows the update's two-product form), ACAMP 2 FMA +
+# 2 mul + 2 min, p = 1 2 sub + 2 add + 2 min, p = 3 2 sub + 2 mul + 2 FMA +
+# 2 min. The FP32 sweep is counted the same way: packed FP32 is not used, so
+# single precision issues at the FP64 lane rate.
+OPS_PER_PAIR = {"aamp": 6, "acamp": 6, "pnorm1": 6, "pnorm3": 8}
+WORKLOADS = ("headline", "extras", "batch", "configs", "long")
+
+
+def ops_per_pair(kind, p=2.0):
+    if kind == "pnorm":
+        return OPS_PER_PAIR["pnorm1"] if p == 1.0 else OPS_PER_PAIR["pnorm3"]
+    return OPS_PER_PAIR[kind]
+
+
+def roofline_frac(ops, sweep_ms):
+    """Fraction of the VALU peak reached by `ops` lane-operations in sweep_ms."""
+    return round(ops / (sweep_ms * 1e-3) / PEAK_LANE_OPS, 4) if sweep_ms > 0 else None
 # HBM traffic of the sweep kernel, from rocprofv3 counters (see that file)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_band_acamp_rw128k_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1901_05708_amd", "csrc", "k_sweep_band.hip")
@@ -50,10 +78,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--only", default="",
+                    help="comma-separated subset of " + ",".join(WORKLOADS) +
+                         " (headline runs whenever extras does); default: all")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
-    ap.add_argument("--configs", action="store_true",
-                    help="also time the other single-series workloads (rw8k, sines p = 1 and 3, "
-                         "ecg ACAMP and AAMP) in both precisions; adds a minute or two")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other single-series workloads (rw8k, sines p = 1 and 3, "
+                         "ecg ACAMP and AAMP)")
+    ap.add_argument("--configs", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-long", action="store_true",
+                    help="skip the long-window (Fig. 4) workloads")
     ap.add_argument("--no-fp32", action="store_true",
                     help="skip the FP32 + refresh and MP_FP32_AUTO runs")
     ap.add_argument("--no-auto", action="store_true", help="skip the MP_FP32_AUTO runs")
@@ -210,10 +244,62 @@ def headline(args, mp, W, torch):
     return res
 
 
+def _time_single(mp, torch, Td, m, kind, p, excl, prec, steps, stream, label):
+    """Autotune (first call), then `steps` timed calls with the library's
+    phase events on: ms per call end to end, the sweep phase's ms, and the
+    shape the autotuner chose."""
+    def step():
+        if kind == "aamp":
+            mp.aamp(Td, m, excl=excl, precision=prec, stream=stream, validate=False)
+        elif kind == "acamp":
+            mp.acamp(Td, m, excl=excl, precision=prec, stream=stream, validate=False)
+        else:
+            mp.pnorm(Td, m, p=p, excl=excl, precision=prec, stream=stream, validate=False)
+    print(f"[bench] {label} {prec}: autotune and timing", file=sys.stderr, flush=True)
+    mp.set_profiling(False)
+    step()                          # autotuner
+    torch.cuda.synchronize()
+    tune = mp.profile_read()["ms_autotune"]
+    mp.set_profiling(True)
+    ms, med = timed(step, steps, 1, stream)
+    prof = mp.profile_read()
+    mp.set_profiling(False)
+    calls = max(1, prof["calls"])
+    return {"ms_per_step": round(ms, 4), "ms_median": round(med, 4),
+            "sweep_ms": round(prof["ms_sweep"] / calls, 4),
+            "finalize_ms": round(prof["ms_finalize"] / calls, 4),
+            "refresh_rows": prof["refresh_rows"], "diags_per_lane": prof["diags_per_lane"],
+            "fp32_jobs": prof["fp32_jobs"], "autotune_ms": round(tune, 1),
+            "fallback_rows_per_step": round(prof["fallback_rows"] / calls, 1)}
+
+
+def _single_row(mp, torch, T, m, kind, p, steps, stream, label, precisions=("fp64", "fp32")):
+    import workloads as W
+    Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
+    excl = W.excl_default(m)
+    pairs = mp.pair_count(len(T), m, excl)
+    ops = ops_per_pair(kind, p) * pairs
+    row = {"n": len(T), "m": m, "kind": kind, "p": p, "pairs": pairs,
+           "ops_per_pair": ops_per_pair(kind, p)}
+    for prec in precisions:
+        r = _time_single(mp, torch, Td, m, kind, p, excl, prec, steps, stream, label)
+        r["value"] = round(pairs / (r["ms_per_step"] * 1e-3) / 1e9, 1)
+        r["sweep_frac"] = roofline_frac(ops, r["sweep_ms"])
+        row[prec] = r
+    if "fp32" in row:
+        row["fp32_gain"] = round(row["fp32"]["value"] / row["fp64"]["value"], 3)
+        row["fp32_sweep_gain"] = round(row["fp64"]["sweep_ms"] / row["fp32"]["sweep_ms"], 3)
+    print(f"[bench] {label}: " + ", ".join(f"{k} {row[k]['value']} Gpairs/s (sweep frac "
+                                            f"{row[k]['sweep_frac']})" for k in precisions),
+          file=sys.stderr, flush=True)
+    return row
+
+
 def other_configs(args, mp, W, torch):
     """The other single-series workloads, each autotuned and then timed over a
-    few calls in FP64 and FP32 + refresh: pairs/s end to end, the FP32 gain and
-    the exact-search rows. Returns a dict keyed by workload."""
+    few calls in FP64 and FP32 + refresh: pairs/s end to end, the sweep's VALU
+    roofline fraction, the FP32 gain and the exact-search rows. Returns a dict
+    keyed by workload."""
     runs = []
     T, m = W.rw8k()
     runs.append(("rw8k_aamp", T, m, "aamp", 2.0, 20))
@@ -226,36 +312,25 @@ def other_configs(args, mp, W, torch):
     stream = torch.cuda.current_stream()
     res = {}
     for name, T, m, kind, p, steps in runs:
-        Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
-        excl = W.excl_default(m)
-        pairs = mp.pair_count(len(T), m, excl)
-        row = {"n": len(T), "m": m, "p": p, "pairs": pairs}
-        for prec in ("fp64", "fp32"):
-            def step():
-                if kind == "aamp":
-                    mp.aamp(Td, m, excl=excl, precision=prec, stream=stream, validate=False)
-                elif kind == "acamp":
-                    mp.acamp(Td, m, excl=excl, precision=prec, stream=stream, validate=False)
-                else:
-                    mp.pnorm(Td, m, p=p, excl=excl, precision=prec, stream=stream, validate=False)
-            print(f"[configs] {name} {prec}: autotune and timing", file=sys.stderr, flush=True)
-            mp.set_profiling(False)
-            step()                          # autotuner
-            torch.cuda.synchronize()
-            mp.set_profiling(True)
-            ms, _ = timed(step, steps, 1, stream)
-            prof = mp.profile_read()
-            mp.set_profiling(False)
-            calls = max(1, prof["calls"])
-            row[prec] = {"ms_per_step": round(ms, 3),
-                         "value": round(pairs / (ms * 1e-3) / 1e9, 1),
-                         "refresh_rows": prof["refresh_rows"],
-                         "diags_per_lane": prof["diags_per_lane"],
-                         "fallback_rows_per_step": round(prof["fallback_rows"] / calls, 1)}
-        row["fp32_gain"] = round(row["fp32"]["value"] / row["fp64"]["value"], 3)
-        res[name] = row
-        print(f"[configs] {name}: fp64 {row['fp64']['value']} fp32 {row['fp32']['value']} Gpairs/s",
-              file=sys.stderr, flush=True)
+        res[name] = _single_row(mp, torch, T, m, kind, p, steps, stream, name,
+                                ("fp64",) if args.no_fp32 else ("fp64", "fp32"))
+    return res
+
+
+def long_windows(args, mp, W, torch):
+    """The paper's second experiment (Sec. 5.2, Fig. 4): n = 2^18 uniform
+    values, the window length doubled from 256 to 65536 (every other power of
+    two), AAMP and ACAMP, both precisions."""
+    T, _ = W.uniform()
+    stream = torch.cuda.current_stream()
+    res = {}
+    for m in (256, 1024, 4096, 16384, 65536):
+        for kind in ("aamp", "acamp"):
+            name = f"uniform_m{m}_{kind}"
+            res[name] = _single_row(mp, torch, T, m, kind, 2.0, 3, stream, name,
+                                    ("fp64",) if args.no_fp32 else ("fp64", "fp32"))
+    res["workload"] = ("uniform U[0,1) n=262144 (seed 6), m in {256, 1024, 4096, 16384, 65536}, "
+                       "excl = ceil(m/4)")
     return res
 
 
@@ -267,8 +342,10 @@ def batch_workload(args, mp, W, torch):
     T_cat = torch.as_tensor(np.concatenate([jb.T for jb in jobs_np]), device="cuda")
     table, total_n, total_out = mp.batch_layout(jobs)
     pairs = sum(mp.pair_count(jb.n, jb.m, mp.default_excl(jb.m)) for jb in jobs)
+    ops = sum(mp.pair_count(jb.n, jb.m, mp.default_excl(jb.m)) *
+              ops_per_pair("aamp" if jb.kind == mp.KIND_AAMP else "acamp") for jb in jobs)
     stream = torch.cuda.current_stream()
-    res = {"jobs": len(jobs), "pairs": pairs, "samples": int(total_n)}
+    res = {"jobs": len(jobs), "pairs": pairs, "samples": int(total_n), "ops_per_pair": 6}
     for prec in ("fp64",) + _lower_precisions(args):
         P = torch.empty(total_out, dtype=torch.float64, device="cuda")
         I = torch.empty(total_out, dtype=torch.int64, device="cuda")
@@ -304,6 +381,8 @@ def batch_workload(args, mp, W, torch):
             "fp32_jobs": prof["fp32_jobs"],
             "phases_ms": {"prep": round(prof["ms_prep"], 3), "sweep": round(prof["ms_sweep"], 3),
                           "finalize": round(prof["ms_finalize"], 3)},
+            # the sweep launches of one directly launched (profiled) call
+            "sweep_frac": roofline_frac(ops, prof["ms_sweep"]),
         }
     if "fp32" in res:
         res["fp32_gain"] = round(res["fp32"]["value"] / res["fp64"]["value"], 4)
@@ -437,6 +516,33 @@ def main():
         print("bench.py needs a HIP GPU", file=sys.stderr)
         sys.exit(1)
     mp.load()
+    only = set(x for x in args.only.split(",") if x)
+    bad = only - set(WORKLOADS)
+    if bad:
+        print(f"unknown workloads {sorted(bad)}; choose from {WORKLOADS}", file=sys.stderr)
+        sys.exit(2)
+    run = set(only or WORKLOADS)
+    if args.no_batch:
+        run.discard("batch")
+    if args.no_configs:
+        run.discard("configs")
+    if args.no_long:
+        run.discard("long")
+    if "extras" in run:
+        run.add("headline")
+    if "headline" not in run:
+        out = {"metric": METRIC, "value": None, "unit": "Gpairs/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "subset: " + ",".join(sorted(run))}}
+        if "batch" in run:
+            out["batch"] = batch_workload(args, mp, W, torch)
+        if "configs" in run:
+            out["configs"] = other_configs(args, mp, W, torch)
+        if "long" in run:
+            out["long_windows"] = long_windows(args, mp, W, torch)
+        print(json.dumps(out), flush=True)
+        return
     h = headline(args, mp, W, torch)
     f64 = h["fp64"]
     pairs = h["pairs"]
@@ -499,6 +605,12 @@ def main():
                                    "sweep": round(f32["sweep_ms"], 4),
                                    "finalize": round(f32["finalize_ms"], 4)},
             "sweep_gain_vs_fp64": round(f64["sweep_ms"] / f32["sweep_ms"], 4),
+            "roofline": {"bound": "alu", "kernel": "k_sweep_band (ACAMP, FP32)",
+                         "achieved": round(ops / (f32["sweep_ms"] * 1e-3) / 1e12, 3),
+                         "peak": round(peak, 3), "unit": "Tlane-ops/s",
+                         "frac": roofline_frac(ops, f32["sweep_ms"]),
+                         "ops_per_pair": OPS_PER_PAIR["acamp"],
+                         "kernel_ms": round(f32["sweep_ms"], 4)},
         }
     if "fp32_auto" in h:
         fa = h["fp32_auto"]
@@ -512,6 +624,33 @@ def main():
             "refresh_rows": fa["refresh_rows"],
             "fallback_rows_per_step": fa["fallback_rows"],
         }
+    if "extras" in run:
+        extras(args, mp, h, torch, out)
+    if "batch" in run:
+        out["batch"] = batch_workload(args, mp, W, torch)
+    if "configs" in run:
+        out["configs"] = other_configs(args, mp, W, torch)
+    if "long" in run:
+        out["long_windows"] = long_windows(args, mp, W, torch)
+    if args.copy_calib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the ones read for the sweep
+        src = torch.ones(args.copy_calib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = int(src.numel() * 8)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(h["T"], h["m"], h["excl"], "acamp", f64["P"], f64["I"],
+                                           args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+def extras(args, mp, h, torch, out):
+    """Motifs and discords, incremental appends, the anytime curve and the F
+    comparator, all on the headline series."""
+    f64 = h["fp64"]
     # motif / discord extraction on the headline profile (k = 10 each)
     Pd = torch.as_tensor(f64["P"], device="cuda")
     Id = torch.as_tensor(f64["I"], device="cuda")
@@ -529,23 +668,6 @@ def main():
     out["incremental"] = incremental(mp, h, torch)
     out["anytime"] = anytime_curve(mp, h, torch)
     out["acamp_fcmp"] = fcmp_variant(args, mp, h, torch)
-    if not args.no_batch:
-        out["batch"] = batch_workload(args, mp, W, torch)
-    if args.configs:
-        out["configs"] = other_configs(args, mp, W, torch)
-    if args.copy_calib > 0:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
-        # calibrate the ones read for the sweep
-        src = torch.ones(args.copy_calib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calib_bytes"] = int(src.numel() * 8)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(h["T"], h["m"], h["excl"], "acamp", f64["P"], f64["I"],
-                                           args.cpu_rows)
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -210,29 +210,41 @@ def test_batch_replays_between_eager_calls(mp):
     assert np.array_equal(P.cpu().numpy(), ref_P) and np.array_equal(I.cpu().numpy(), ref_I)
 
 
-@pytest.mark.slow
-def test_batch_full_workload_sampled(mp):
+def test_batch_full_workload(mp):
     """The full 512-series batch workload (3.9e11 pairs) in one call, FP64 and
-    FP32 + refresh; the oracle checks 24 random series on 32 sampled rows each
-    and every series on its first row."""
+    FP32 + refresh, against the oracle's stored rows: 32 rows of every series
+    and 256 of 64 series (tests/golden/fullsize/batch512.npz); FP32 also on
+    every row against FP64."""
+    from tests import fullsize_refs as R
     jobs = W.batch()
+    ref = R.load("batch512", series=[jb.T for jb in jobs])
     specs = [(jb.T, jb.m, jb.kind, 2.0, 0, 0) for jb in jobs]
-    rng = np.random.default_rng(12)
-    pick = set(rng.choice(len(specs), size=24, replace=False).tolist())
+    out = {}
     for prec, rtol in (("fp64", 1e-9), ("fp32", 1e-4)):
         _note(f"batch full workload {prec} jobs={len(specs)}")
         P, I, _ = _run(mp, specs, precision=prec)
         P, I = P.cpu().numpy(), I.cpu().numpy()
+        out[prec] = P
         off = 0
-        for b, (T, m, kind, p, excl, R) in enumerate(specs):
+        for b, (T, m, kind, p, excl, R_) in enumerate(specs):
             N = len(T) - m + 1
             e = W.excl_default(m)
-            rows = W.sample_rows(N, 32, seed=b) if b in pick else np.array([0])
-            Pr, Ir, Qr = oracle.profile(T, m, kind, excl=e, rows=rows)
-            check_profile(T, m, kind, 2.0, e, P[off:off + N][rows], I[off:off + N][rows], Pr, Ir,
-                          Qr, rtol, 1e-6 if kind == "acamp" else 0.0, rows=rows, sample=8,
+            sel = ref["job"] == b
+            rows = ref["rows"][sel]
+            assert len(rows) >= 32
+            check_profile(T, m, kind, 2.0, e, P[off:off + N][rows], I[off:off + N][rows],
+                          ref["P"][sel], ref["I"][sel], ref["Q"][sel], rtol,
+                          1e-6 if kind == "acamp" else 0.0, rows=rows, sample=8,
                           label=f"full-{prec} job {b}")
             off += N
+        _note(f"batch {prec}: {len(ref['rows'])} oracle rows over {len(specs)} series match")
+    kinds = np.concatenate([np.full(len(jb.T) - jb.m + 1, jb.kind == "acamp") for jb in jobs])
+    P32, P64 = out["fp32"], out["fp64"]
+    assert np.array_equal(np.isinf(P32), np.isinf(P64))
+    fin = np.isfinite(P64)
+    tol = 1e-4 * P64 + np.where(kinds, 1e-6, 0.0)
+    bad = np.nonzero(fin & (np.abs(P32 - P64) > tol))[0]
+    assert bad.size == 0, f"{bad.size} FP32 rows beyond 1e-4 of FP64, e.g. {bad[:10]}"
 
 
 def test_fp32_wide_bands_with_short_windows(mp, monkeypatch):

@@ -1,7 +1,13 @@
 """Parity at the full workload sizes, in the launch configuration bench.py
-times: the GPU computes the whole profile, the oracle checks sampled rows
-(random rows plus the structurally interesting ones: motifs, constant-run
-boundaries, anomalies)."""
+times (R = 0, autotuned): the GPU computes the whole profile and the oracle's
+answers on seeded row samples (random rows plus the structurally interesting
+ones: motifs, constant-run boundaries, anomalies, earlier FP32 misses) are
+read from tests/golden/fullsize/, written by
+tests/golden/make_fullsize_refs.py with the oracle alone. Coverage per
+workload: random walk 131072 ACAMP 4096 + 252 rows, AAMP 1024 + 257; sines
+4096 rows per p; ECG 4096 + 25 rows per kind; uniform 2^18 with m = 16384 /
+65536: 256 / 64 rows per kind. Every FP32 profile is also checked on every row
+against the FP64 sweep."""
 import sys
 
 import numpy as np
@@ -9,6 +15,7 @@ import pytest
 
 import oracle
 import workloads as W
+from tests import fullsize_refs as R
 from tests.parity import check_profile
 
 pytestmark = pytest.mark.gpu
@@ -54,28 +61,72 @@ def _sampled(mp, kind, T, m, rows, p=2.0, precision="fp64", label=""):
     return info, P, I
 
 
-def test_rw128k_acamp_fp64_sampled(mp):
-    """The bench workload: constant runs -> +inf rows, motifs found."""
+def _against_ref(name, T, m, kind, p, P, I, precision, label, min_rows):
+    """The GPU profile on the rows of a stored oracle file (see
+    tests/fullsize_refs.py), at the tolerance of the precision."""
+    ref = R.load(name, T=T)
+    rows = ref["rows"]
+    assert len(rows) >= min_rows, f"{name}: only {len(rows)} oracle rows stored"
+    excl = W.excl_default(m)
+    rtol = 1e-9 if precision == "fp64" else 1e-4
+    atol = 1e-6 if kind == "acamp" else 0.0
+    info = check_profile(T, m, kind, p, excl, P[rows], I[rows], ref["P"], ref["I"], ref["Q"],
+                         rtol, atol, rows=rows, label=label)
+    _note(f"{label}: {len(rows)} oracle rows match ({info['index_mismatch']} near-tie indices)")
+    return info
+
+
+def _fp32_every_row(P32, P64, kind, label):
+    """The FP32 sweep's profile-value contract on every row, against the FP64
+    sweep (itself checked against the oracle at 1e-9 on the sampled rows):
+    the same rows are infinite, and every finite value is within 1e-4."""
+    inf32, inf64 = np.isinf(P32), np.isinf(P64)
+    assert np.array_equal(inf32, inf64), f"{label}: finiteness differs at {np.nonzero(inf32 != inf64)[0][:10]}"
+    fin = ~inf64
+    atol = 1e-6 if kind == "acamp" else 0.0
+    err = np.abs(P32[fin] - P64[fin]) - (1e-4 * P64[fin] + atol)
+    bad = np.nonzero(err > 0)[0]
+    assert bad.size == 0, (f"{label}: {bad.size} FP32 rows beyond 1e-4, e.g. rows "
+                           f"{np.nonzero(fin)[0][bad[:10]]}")
+    _note(f"{label}: all {int(fin.sum())} finite rows of the FP32 sweep within 1e-4 of FP64")
+
+
+def test_rw128k_acamp(mp):
+    """The headline workload (ACAMP, constant runs, planted motifs) in both
+    precisions: 4096 random rows, the motif rows and every run boundary
+    against the oracle; FP32 also on every row against FP64."""
     T, m, planted = W.rw128k()
     N = len(T) - m + 1
-    rows = list(W.sample_rows(N, 384, seed=11))
-    for a, b in planted.motifs:
-        rows += [a, b]
-    for s, L in planted.runs:
-        rows += [max(0, s - m), max(0, s - m // 2), s - 1 if s > 0 else 0, s,
-                 min(N - 1, s + L - m), min(N - 1, s + L - m + 1), min(N - 1, s + L - 1)]
-    info, P, I = _sampled(mp, "acamp", T, m, rows, label="rw128k")
-    for s, L in planted.runs:
-        inside = np.arange(s, s + L - m + 1)
-        assert np.all(np.isinf(P[inside])) and np.all(I[inside] == -1)
-    const = np.zeros(N, dtype=bool)
-    for s, L in planted.runs:
-        const[s:s + L - m + 1] = True
-    assert not np.any(const[I[I >= 0]])
-    for a, b in planted.motifs:
-        assert I[a] == b and I[b] == a
-    fin = np.isfinite(P)
-    assert np.all(P[fin] >= 0)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        _note(f"rw128k acamp {prec}")
+        P, I = _gpu(mp, "acamp", T, m, precision=prec)
+        _against_ref("rw128k_acamp", T, m, "acamp", 2.0, P, I, prec, f"rw128k-acamp-{prec}", 4096)
+        for s, L in planted.runs:
+            inside = np.arange(s, s + L - m + 1)
+            assert np.all(np.isinf(P[inside])) and np.all(I[inside] == -1)
+        const = np.zeros(N, dtype=bool)
+        for s, L in planted.runs:
+            const[s:s + L - m + 1] = True
+        assert not np.any(const[I[I >= 0]])
+        for a, b in planted.motifs:
+            assert I[a] == b and I[b] == a
+        out[prec] = P
+    _fp32_every_row(out["fp32"], out["fp64"], "acamp", "rw128k-acamp")
+
+
+def test_rw128k_aamp(mp):
+    """The headline series under the pure Euclidean distance, both
+    precisions, on 1024 random rows plus the motif and run rows and the row
+    an earlier FP32 sweep left 2.79e-4 above its minimum (113495)."""
+    T, m, planted = W.rw128k()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        _note(f"rw128k aamp {prec}")
+        P, I = _gpu(mp, "aamp", T, m, precision=prec)
+        _against_ref("rw128k_aamp", T, m, "aamp", 2.0, P, I, prec, f"rw128k-aamp-{prec}", 1024)
+        out[prec] = P
+    _fp32_every_row(out["fp32"], out["fp64"], "aamp", "rw128k-aamp")
 
 
 def test_rw8k_aamp_full(mp):
@@ -87,57 +138,56 @@ def test_rw8k_aamp_full(mp):
 
 
 @pytest.mark.parametrize("p", [1.0, 3.0])
-def test_sines_pnorm_sampled(mp, p):
+def test_sines_pnorm(mp, p):
+    """The sines workload, 4096 rows per p in both precisions (p = 3 with the
+    row an earlier FP32 sweep left 1.004e-4 above its minimum, 30128), FP32
+    also on every row against FP64."""
     T, m = W.sines()
-    N = len(T) - m + 1
-    _sampled(mp, "pnorm", T, m, W.sample_rows(N, 256, seed=int(p)), p=p, label=f"sines-p{p}")
+    out = {}
+    for prec in ("fp64", "fp32"):
+        _note(f"sines p={p} {prec}")
+        P, I = _gpu(mp, "pnorm", T, m, p=p, precision=prec)
+        _against_ref(f"sines_p{int(p)}", T, m, "pnorm", p, P, I, prec, f"sines-p{p}-{prec}", 4096)
+        out[prec] = P
+    _fp32_every_row(out["fp32"], out["fp64"], "pnorm", f"sines-p{p}")
 
 
 @pytest.mark.parametrize("kind", ["acamp", "aamp"])
-def test_ecg_2m_sampled(mp, kind):
+def test_ecg_2m(mp, kind):
+    """The 2,097,152-sample ECG-like series (2.2e12 pairs per kind), both
+    precisions: 4096 random rows plus the rows around every anomalous beat
+    against the oracle, FP32 also on every row against FP64."""
     T, m, anomalies = W.ecg()
-    N = len(T) - m + 1
-    rows = list(W.sample_rows(N, 48, seed=5))
-    for c in anomalies:
-        rows += [max(0, c - m // 2)]
-    _sampled(mp, kind, T, m, rows, label=f"ecg-{kind}")
+    out = {}
+    for prec in ("fp64", "fp32"):
+        _note(f"ecg {kind} {prec}")
+        P, I = _gpu(mp, kind, T, m, precision=prec)
+        _against_ref(f"ecg_{kind}", T, m, kind, 2.0, P, I, prec, f"ecg-{kind}-{prec}", 1024)
+        out[prec] = P
+    _fp32_every_row(out["fp32"], out["fp64"], kind, f"ecg-{kind}")
+
+
+@pytest.mark.parametrize("m", [16384, 65536])
+@pytest.mark.parametrize("kind", ["aamp", "acamp"])
+def test_uniform_long_windows(mp, m, kind):
+    """The paper's second experiment (Sec. 5.2, Fig. 4): n = 2^18 uniform
+    values with long windows, 256 oracle rows at m = 16384 and 64 at
+    m = 65536, both precisions."""
+    T, _ = W.uniform()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        _note(f"uniform n=2^18 m={m} {kind} {prec}")
+        P, I = _gpu(mp, kind, T, m, precision=prec)
+        _against_ref(f"uniform_m{m}_{kind}", T, m, kind, 2.0, P, I, prec,
+                     f"uniform-m{m}-{kind}-{prec}", 64)
+        out[prec] = P
+    _fp32_every_row(out["fp32"], out["fp64"], kind, f"uniform-m{m}-{kind}")
 
 
 def test_uniform_paper_shape_sampled(mp):
     T, m = W.uniform()
     N = len(T) - m + 1
     _sampled(mp, "acamp", T, m, W.sample_rows(N, 128, seed=6), label="uniform")
-
-
-@pytest.mark.parametrize("kind", ["acamp", "aamp"])
-def test_rw128k_fp32_sampled(mp, kind):
-    """FP32 sweep with FP64 restarts on the bench workload: values within
-    1e-4 relative of the oracle, indices equal unless the runner-up is within
-    that bound."""
-    T, m, planted = W.rw128k()
-    N = len(T) - m + 1
-    rows = list(W.sample_rows(N, 384, seed=12))
-    for a, b in planted.motifs:
-        rows += [a, b]
-    info, P, I = _sampled(mp, kind, T, m, rows, precision="fp32", label=f"rw128k-fp32-{kind}")
-    if kind == "acamp":
-        for a, b in planted.motifs:
-            assert I[a] == b and I[b] == a
-
-
-@pytest.mark.parametrize("p", [1.0, 3.0])
-def test_sines_pnorm_fp32_sampled(mp, p):
-    T, m = W.sines()
-    N = len(T) - m + 1
-    _sampled(mp, "pnorm", T, m, W.sample_rows(N, 256, seed=20 + int(p)), p=p, precision="fp32",
-             label=f"sines-fp32-p{p}")
-
-
-def test_ecg_fp32_sampled(mp):
-    T, m, anomalies = W.ecg()
-    N = len(T) - m + 1
-    rows = list(W.sample_rows(N, 48, seed=7)) + [max(0, c - m // 2) for c in anomalies]
-    _sampled(mp, "acamp", T, m, rows, precision="fp32", label="ecg-fp32")
 
 
 @pytest.mark.skipif(not __import__("os").environ.get("MP_FULL_ORACLE"),
