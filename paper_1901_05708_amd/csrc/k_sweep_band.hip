@@ -445,7 +445,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         // column whose last diagonal in this lane was d = 0 moves one lane
         // down and lane 0's enters the history register.
         // The accumulator of diagonal d lives in slot (sbase + d) % KD.
-        auto reduce_step = [&](int tau, int sbase, const F (&v)[KD]) {
+        auto reduce_step = [&](int row_slot, int sbase, const F (&v)[KD]) {
             F key[KD];
 #pragma unroll
             for (int d = 0; d < KD; ++d) {
@@ -456,7 +456,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
             for (int ww = 1; ww < KD; ww *= 2)
 #pragma unroll
                 for (int d = 0; d + ww < KD; d += 2 * ww) key[d] = P::kmin(key[d], key[d + ww]);
-            rowbuf[((tau + 1) & (NRB - 1)) * 64 + lane] = key[0];
+            rowbuf[row_slot * 64 + lane] = key[0];
             const F done = colacc[sbase % KD];
             colacc[sbase % KD] = P::shift_down_inf(done);
             hist = P::shift_up_keep(hist, done);
@@ -505,7 +505,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
 #pragma unroll
             for (int d = 0; d < KD; ++d)
                 v[d] = (KIND == ACAMP) ? acamp_key<PC, F>(S[d], rinv0, sz[jb + d]) : S[d];
-            reduce_step(-1, 0, v);
+            reduce_step(0, 0, v);
         }
         flush_cols(0, 1);   // column 0 has only the first row's pair
         // Pair-visit count (test mode): the real pairs (j < N) of every step
@@ -596,7 +596,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                         v[d] = acamp_key<PC, F>(S[d], rinv, cz[sl]);
                     }
                 }
-                reduce_step(tau, q + 1, v);
+                reduce_step((q + 1) & (NRB - 1), q + 1, v);
                 count_row(i0 + 1 + tau);
                 if (q == KD - 1) {
                     // next block's row operands (rows past i1 read padding entries)
