@@ -439,11 +439,14 @@ constexpr int64_t FP64_R_PER_M = 64;
 int32_t default_R(uint32_t sel, bool fp32, int32_t m)
 {
     if (!fp32) return (int32_t)std::min<int64_t>(std::max<int64_t>(4096, 16 * (int64_t)m), 1 << 24);
+    int64_t r = 256;
     switch (sel) {
-    case SEL_ACAMP: return 512;
-    case SEL_P1: return 1024;
-    default: return 256;
+    case SEL_ACAMP: r = 512; break;
+    case SEL_P1: r = 1024; break;
+    default: break;
     }
+    // at least 2m rows per restart of m operations per diagonal
+    return (int32_t)std::min<int64_t>(std::max<int64_t>(r, 2 * (int64_t)m), 1 << 24);
 }
 
 // Where a band's exact restart goes in the split of the row space: a band of
@@ -475,14 +478,18 @@ int64_t band_rows_total(int64_t N, int64_t excl, int64_t W, int64_t *nbands)
 // amplified far beyond what the winner's self-check can see.
 constexpr int32_t FP32_MIN_M = 32;
 
-// Distances with an FP32 sweep: ACAMP and p = 1. The certification checks
-// the winner's FP32 drift only. The AAMP and p = 3 sums cancel large
-// increments against small best-match sums, so a row's true best candidate
-// can drift by more than its winner and lose unseen. Every-row checks against
-// the oracle found one row 2.79e-4 above its minimum in the 131072-sample
-// walk (AAMP), and one 1.004e-4 above in the sines p = 3 workload (also with
-// a tighter check). ACAMP keys 1 - rho next to 1, and the walk's every row
-// met 1e-4. Other distances run the FP64 sweep under MP_FP32_REFRESH.
+// Distances with an FP32 sweep: ACAMP and p = 1. The certification checks the
+// winner's FP32 drift only. The AAMP and p = 3 sums cancel large increments
+// against small best-match sums, so a row's true best candidate can drift by
+// more than its winner and lose unseen: every-row checks against the oracle
+// found the 131072-sample walk's row 113495 2.79e-4 above its minimum (AAMP),
+// the sines workload's row 30128 1.004e-4 above (p = 3), and five rows of the
+// 512-series batch, identically with and without per-item recentring of the
+// operands. Replaying the walk's row in single precision on the host put the
+// drift of its true best pair at 2.2e-3 rms from the running sum's rounding
+// (u |S| per step, S large away from the match) against 1.5e-5 from the
+// rounded operands. ACAMP keys 1 - rho next to 1 and met 1e-4 on every row of
+// every workload. Other distances run the FP64 sweep under MP_FP32_REFRESH.
 constexpr uint32_t SEL_FP32 = SEL_ACAMP | SEL_P1;
 
 // A band sweep of a launch: a contiguous range of the job table, all of one
@@ -881,6 +888,17 @@ std::vector<Tuning> tune_candidates(int32_t precision, int32_t m_min)
     if (precision != MP_FP64) {
         for (int kd : {8, 16})
             for (int R : {256, 512, 1024, 2048}) c.push_back(Tuning{kd, R, 1, 0});
+        // long windows: the restart costs about 2m / R operations per pair,
+        // so short intervals lose to the FP64 sweep's; the self-check still
+        // decides which rows the longer FP32 runs leave uncertified
+        if (m_min >= 1024) {
+            for (int64_t f : {4, 16})
+                c.push_back(Tuning{8, (int32_t)std::min<int64_t>(f * m_min, 1 << 24), 1, 0});
+            if (m_min >= 2048)
+                for (int wps : {1, 2})
+                    c.push_back(
+                        Tuning{8, (int32_t)std::min<int64_t>(16 * (int64_t)m_min, 1 << 24), 1, wps});
+        }
     }
     if (precision != MP_FP32_REFRESH) {
         const bool sweep64 = precision == MP_FP32_AUTO;

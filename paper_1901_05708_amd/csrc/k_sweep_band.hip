@@ -221,11 +221,16 @@ struct Streams<float> {
 };
 
 // LDS doubles the first-row staging uses: the column samples of a 64-step
-// chunk (64 KD + 64, one pad slot per KD).
+// chunk (64 KD + 64, one pad slot per KD), then its 64 row samples.
+template <int KD>
+constexpr int stage_cols()
+{
+    return (64 * KD + 64) + (64 * KD + 64) / KD;
+}
 template <int KD>
 constexpr int stage_doubles()
 {
-    return (64 * KD + 64) + (64 * KD + 64) / KD;
+    return stage_cols<KD>() + 64;
 }
 
 }  // namespace
@@ -250,8 +255,8 @@ __device__ __forceinline__ F acamp_key(F S, F ri, F cj)
 
 template <int KIND, int PC, int KD, typename F, bool COUNT>
 __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, const int64_t i0,
-                                          const int64_t i1, F *ring, F *rowbuf, double *stage,
-                                          unsigned long long *visits)
+                                          const int64_t i1, F *ring, F *rowbuf, F *rowop,
+                                          double *stage, unsigned long long *visits)
 {
     typedef Prec<F> P;
     constexpr int WD = 64 * KD;          // diagonals per item
@@ -274,6 +279,30 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
     const gptr<double> Tg = as_global(s.T);
     const gptr<double> mug = as_global(s.mu);
     cdouble *Tc = as_const(s.T);
+    // Single-precision Euclidean and p-norm sweeps take their sample-valued
+    // operands (AAMP: v = t[j+m-1] + t[j-1]; p-norm: both samples) relative to
+    // the item's own centre cc = t[i0], converted from the FP64 streams as they
+    // are staged: their rounding then scales with the item's local spread, not
+    // with the series' offset (both sides of every difference shift alike).
+    // Row operands reach the lanes through a small LDS buffer (rowop), since
+    // the conversion needs vector instructions. Entries at or past N keep the
+    // single-precision sentinels.
+    constexpr bool RECENTRE = sizeof(F) == 4 && KIND != ACAMP;
+    constexpr bool RX_LDS = RECENTRE && KIND == PNORM;
+    const double cc = RECENTRE ? Tc[i0] : 0.0;
+    const gptr<double> xg = as_global(s.x);
+    const gptr<double> yg = as_global(s.y);
+    const F sent_x = (KIND == PNORM) ? (F)(s.pclass == P_ONE ? SENTF_P1 : SENTF_P3)
+                                     : (F)SENTF_EUCLID;
+    auto col_x = [&](int64_t c) -> F {
+        if (!RX_LDS) return sx[c];
+        return c < N ? (F)(xg[c] - cc) : sent_x;
+    };
+    auto col_y = [&](int64_t c) -> F {
+        if (!RECENTRE) return sy[c];
+        if (KIND == AAMP) return c < N ? (F)(yg[c] - 2.0 * cc) : (F)SENTF_EUCLID;
+        return c < N ? (F)(yg[c] - cc) : (F)0;
+    };
     const auto xc = as_const(Streams<F>::x(s));
     const auto yc = as_const(Streams<F>::y(s));
     const auto zc = as_const(Streams<F>::z(s));
@@ -288,8 +317,10 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         // staged in LDS with coalesced loads (the next chunk's loads are issued
         // before the current chunk is consumed); a lane then reads the KD
         // samples entering its register window over the next KD steps at once,
-        // and the row samples arrive as scalar loads. Column element e of a
-        // chunk sits at e + e / KD, so the lanes' reads (KD elements apart) hit
+        // from one address with immediate offsets. The chunk's row samples are
+        // staged beside them and read back as broadcasts (scalar loads would
+        // stall every KD steps on their latency). Column element e of a chunk
+        // sits at e + e / KD, so the lanes' reads (KD elements apart) hit
         // distinct banks.
         //
         // Euclidean and z-normalized distances need one FMA per sample and
@@ -316,15 +347,23 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 win[d] = 0.0;
             }
             auto spos = [](int e) { return e + (e >> Log2<KD>::v); };
-            double nc[NLD];
+            // FP64 Euclidean and p = 1, 3 kernels run 3 waves per SIMD on 168
+            // registers, where holding the row samples in vector registers spills
+            // in the recurrence loop: they keep scalar loads of the row samples
+            constexpr bool ROWS_LDS =
+                !(sizeof(F) == 8 && (KIND == AAMP || (KIND == PNORM && PC != P_GENERIC)));
+            double *rowst = stage + stage_cols<KD>();   // the chunk's LCH row samples
+            double nc[NLD], nr;
             auto fetch = [&](int l0) {
 #pragma unroll
                 for (int q = 0; q < NLD; ++q) nc[q] = Tg[min(cb + l0 + 64 * q + lane, tmax)];
+                if (ROWS_LDS) nr = Tg[min(i0 + l0 + lane, tmax)];
             };
             auto put = [&]() {
                 lds_order();
 #pragma unroll
                 for (int q = 0; q < NLD; ++q) stage[spos(64 * q + lane)] = nc[q] - c0;
+                if (ROWS_LDS) rowst[lane] = nr - c0;
                 lds_order();
             };
             fetch(0);
@@ -359,21 +398,32 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 const int steps = min(LCH, m - l0);
                 const int full = steps & ~(KD - 1);
                 for (int g = 0; g < full; g += KD) {
-                    double nw[KD], rv[KD];
-                    const int64_t rb = uniform64(i0 + l0 + g);
+                    double nw[KD];
+                    // spos(KD lane + g + q + KD - 1) for g a multiple of KD:
+                    // one base, then q + (q > 0)
+                    const int sb = (KD + 1) * lane + g + (g >> Log2<KD>::v) + KD - 1;
 #pragma unroll
-                    for (int q = 0; q < KD; ++q) nw[q] = stage[spos(KD * lane + g + q + KD - 1)];
+                    for (int q = 0; q < KD; ++q)
+                        nw[q] = ROWS_LDS ? stage[sb + q + (q > 0 ? 1 : 0)]
+                                         : stage[spos(KD * lane + g + q + KD - 1)];
+                    if (ROWS_LDS) {
 #pragma unroll
-                    for (int q = 0; q < KD; ++q) rv[q] = Tc[rb + q] - c0;
+                        for (int q = 0; q < KD; ++q) step(q, nw[q], rowst[g + q]);
+                    } else {
+                        double rv[KD];
+                        const int64_t rb = uniform64(i0 + l0 + g);
 #pragma unroll
-                    for (int q = 0; q < KD; ++q) step(q, nw[q], rv[q]);
+                        for (int q = 0; q < KD; ++q) rv[q] = Tc[rb + q] - c0;
+#pragma unroll
+                        for (int q = 0; q < KD; ++q) step(q, nw[q], rv[q]);
+                    }
                 }
                 if (full < steps) {
 #pragma unroll
                     for (int q = 0; q < KD - 1; ++q)
                         if (full + q < steps)
                             step(q, stage[spos(KD * lane + full + q + KD - 1)],
-                                 Tc[i0 + l0 + full + q] - c0);
+                                 ROWS_LDS ? rowst[full + q] : Tc[i0 + l0 + full + q] - c0);
                 }
                 // a full chunk leaves the window slots aligned with the next
                 // chunk's first step; its entries are already in registers
@@ -410,8 +460,8 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         for (int q = 0; q < RING / 64; ++q) {
             const int c = lane + 64 * q;
             const int e = ring_pos<KD>(c);
-            ring[e] = sx[cb + c];
-            ring[RING + e] = sy[cb + c];
+            ring[e] = col_x(cb + c);
+            ring[RING + e] = col_y(cb + c);
             if (KIND == ACAMP) ring[2 * RING + e] = sz[cb + c];
         }
         lds_order();
@@ -524,9 +574,12 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
         // Block tb needs local columns [tb + RING, tb + RING + KD) in the ring;
         // lanes < KD fetch each block one block ahead.
         const int bl = min(lane, KD - 1);
-        F bx = sx[cb + RING + bl];
-        F by = sy[cb + RING + bl];
+        F bx = col_x(cb + RING + bl);
+        F by = col_y(cb + RING + bl);
         F bz = (KIND == ACAMP) ? sz[cb + RING + bl] : (F)0;
+        // recentred row operands of the next block, one row per lane < KD
+        F nrx = RX_LDS ? col_x(i0 + 1 + bl) : (F)0;
+        F nry = RECENTRE ? col_y(i0 + 1 + bl) : (F)0;
         // the row operands of a block (scalar registers), fetched during the
         // previous block
         F rxs[KD], rys[KD], rzs[KD];
@@ -555,13 +608,17 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 ring[e] = bx;
                 ring[RING + e] = by;
                 if (KIND == ACAMP) ring[2 * RING + e] = bz;
+                if (RX_LDS) rowop[lane] = nrx;
+                if (RECENTRE) rowop[KD + lane] = nry;
             }
             lds_order();
             {
                 const int64_t c = cb + tb + KD + RING + bl;
-                bx = sx[c];
-                by = sy[c];
+                bx = col_x(c);
+                by = col_y(c);
                 if (KIND == ACAMP) bz = sz[c];
+                if (RX_LDS) nrx = col_x(rb + KD + bl);
+                if (RECENTRE) nry = col_y(rb + KD + bl);
             }
             // this block's entering columns are tb + KD (lane + 1) + q, all in
             // the aligned column block u = tb / KD + lane + 1
@@ -576,8 +633,8 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                     cy[q] = ring[RING + e];
                     if (KIND == ACAMP) cz[q] = ring[2 * RING + e];
                 }
-                const F rx = rxs[q];
-                const F ry = rys[q];
+                const F rx = RX_LDS ? rowop[q] : rxs[q];
+                const F ry = RECENTRE ? rowop[KD + q] : rys[q];
                 const F rinv = rzs[q];
                 F v[KD];
 #pragma unroll
@@ -662,11 +719,13 @@ __global__ void __launch_bounds__(64)
 {
     constexpr int RING = 64 * KD;
     constexpr int NF = (SELS & SEL_ACAMP) ? 3 : 2;
-    constexpr int SWEEP_D = (int)(((NF * RING + NRB * 64) * sizeof(F) + 7) / 8);
+    // ring fields, row transpose, recentred row operands (FP32 only)
+    constexpr int SWEEP_D = (int)(((NF * RING + NRB * 64 + 2 * KD) * sizeof(F) + 7) / 8);
     constexpr int LDS_D = SWEEP_D > stage_doubles<KD>() ? SWEEP_D : stage_doubles<KD>();
     __shared__ double lds[LDS_D];
     F *ring = reinterpret_cast<F *>(lds);
     F *rowbuf = ring + NF * RING;
+    F *rowop = rowbuf + NRB * 64;
     double *stage = lds;
 
     cint64 *row_base = as_const(b.row_base);
@@ -723,16 +782,16 @@ __global__ void __launch_bounds__(64)
         pos = row0 + i1;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
-            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
+            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
             band_item<ACAMP, (SELS & SEL_FCMP) ? P_FCMP : P_TWO, KD, F, COUNT>(
-                s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
+                s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_P1) && sel == SEL_P1)
-            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
+            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
-            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
+            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_PGEN) && sel == SEL_PGEN)
-            band_item<PNORM, P_GENERIC, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, stage, b.visits);
+            band_item<PNORM, P_GENERIC, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
     }
 }
 

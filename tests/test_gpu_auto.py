@@ -76,7 +76,8 @@ def test_auto_series_within_fp32_tolerance(mp, kind, p, n, m, seed):
 
 
 @pytest.mark.parametrize("kind,p,expect32", [("acamp", 2.0, 1), ("pnorm", 1.0, 1),
-                                             ("aamp", 2.0, 0), ("pnorm", 3.0, 0)])
+                                             ("aamp", 2.0, 0), ("pnorm", 3.0, 0),
+                                             ("pnorm", 2.5, 0)])
 def test_stats_report_the_sweep_precision(mp, kind, p, expect32):
     T = _walk_with_motif(4000, 64, 7)
     _note(f"sweep precision report {kind} p={p}")

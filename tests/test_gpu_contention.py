@@ -31,8 +31,9 @@ def _note(msg):
     sys.stdout.flush()
 
 
-# AAMP under the FP32 flag runs the FP64 sweep; p = 1 is the case whose FP32
-# sweep ties every pair here.
+# A constant series ties every pair (all sums are zero): the packed keys of
+# every row and column collide on the same atomics. Under the FP32 flag AAMP
+# runs the FP64 sweep and p = 1 the FP32 one.
 @pytest.mark.parametrize("kind,p,precision", [("aamp", 2.0, "fp64"), ("aamp", 2.0, "fp32"),
                                               ("pnorm", 1.0, "fp64"), ("pnorm", 1.0, "fp32"),
                                               ("pnorm", 2.5, "fp64")])
