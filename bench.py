@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--only", default="",
                     help="comma-separated subset of " + ",".join(WORKLOADS) +
                          " (headline runs whenever extras does); default: all")
+    ap.add_argument("--names", default="",
+                    help="comma-separated subset of the configs / long-window workload names "
+                         "(e.g. ecg_acamp,uniform_m65536_aamp); default: all")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other single-series workloads (rw8k, sines p = 1 and 3, "
@@ -310,8 +313,11 @@ def other_configs(args, mp, W, torch):
     runs.append(("ecg_acamp", T, m, "acamp", 2.0, 2))
     runs.append(("ecg_aamp", T, m, "aamp", 2.0, 2))
     stream = torch.cuda.current_stream()
+    names = set(x for x in args.names.split(",") if x)
     res = {}
     for name, T, m, kind, p, steps in runs:
+        if names and name not in names:
+            continue
         res[name] = _single_row(mp, torch, T, m, kind, p, steps, stream, name,
                                 ("fp64",) if args.no_fp32 else ("fp64", "fp32"))
     return res
@@ -323,10 +329,13 @@ def long_windows(args, mp, W, torch):
     two), AAMP and ACAMP, both precisions."""
     T, _ = W.uniform()
     stream = torch.cuda.current_stream()
+    names = set(x for x in args.names.split(",") if x)
     res = {}
     for m in (256, 1024, 4096, 16384, 65536):
         for kind in ("aamp", "acamp"):
             name = f"uniform_m{m}_{kind}"
+            if names and name not in names:
+                continue
             res[name] = _single_row(mp, torch, T, m, kind, 2.0, 3, stream, name,
                                     ("fp64",) if args.no_fp32 else ("fp64", "fp32"))
     res["workload"] = ("uniform U[0,1) n=262144 (seed 6), m in {256, 1024, 4096, 16384, 65536}, "

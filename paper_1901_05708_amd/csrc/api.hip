@@ -560,8 +560,9 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
     L.count = env_int("MP_COUNT_PAIRS", 0) == 1;
 
     // Classes of jobs: band jobs by precision and specialisation (index
-    // 64 fp32 + selector bits, so FP64 classes come first), then the rest.
-    constexpr int NCLS = 129, OTHER = 128;
+    // 128 fp32 + selector and launch-flag bits, so FP64 classes come first),
+    // then the rest.
+    constexpr int NCLS = 257, OTHER = 256;
     std::vector<Job> cls[NCLS];
     std::vector<int64_t> rows_of[NCLS];  // band rows
     std::vector<int64_t> pos_of[NCLS];   // positions in the row space (rows + restart costs)
@@ -627,7 +628,10 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         else
             L.pairs += pair_count(s.N, s.excl);
         L.items += nb + (band ? rows / j.seg_rows : 0);
-        const int c = band ? 64 * s.fp32 + (int)(sel | (s.fcmp ? SEL_FCMP : 0u)) : OTHER;
+        const bool longw = !s.fp32 && s.m >= LONG_WINDOW && (sel & (SEL_AAMP | SEL_P1 | SEL_P3));
+        const int c = band ? 128 * s.fp32 + (int)(sel | (s.fcmp ? SEL_FCMP : 0u) |
+                                                  (longw ? SEL_LONG : 0u))
+                           : OTHER;
         cls[c].push_back(j);
         rows_of[c].push_back(rows);
         pos_of[c].push_back(rows + nb * (int64_t)j.band_cost);
@@ -640,8 +644,8 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
             g.first = (int32_t)L.jobs.size();
             g.count = (int32_t)cls[c].size();
             g.rb_off = (int64_t)L.row_base.size();
-            g.sels = (uint32_t)(c & 63);
-            g.fp32 = c >= 64;
+            g.sels = (uint32_t)(c & 127);
+            g.fp32 = c >= 128;
             g.kd = g.fp32 ? kd : 8;
             L.groups.push_back(g);
         }

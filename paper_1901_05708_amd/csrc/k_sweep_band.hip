@@ -253,7 +253,11 @@ __device__ __forceinline__ F acamp_key(F S, F ri, F cj)
     return fma(S * ri, cj, (F)1);
 }
 
-template <int KIND, int PC, int KD, typename F, bool COUNT>
+// ROWS_LDS: the restart stages each chunk's row samples in LDS and reads them
+// back as broadcasts; otherwise it takes them as scalar loads (the kernels
+// that run 3 waves per SIMD on 168 registers, where holding them in vector
+// registers spills in the recurrence loop).
+template <int KIND, int PC, int KD, typename F, bool COUNT, bool ROWS_LDS>
 __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, const int64_t i0,
                                           const int64_t i1, F *ring, F *rowbuf, F *rowop,
                                           double *stage, unsigned long long *visits)
@@ -347,11 +351,6 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
                 win[d] = 0.0;
             }
             auto spos = [](int e) { return e + (e >> Log2<KD>::v); };
-            // FP64 Euclidean and p = 1, 3 kernels run 3 waves per SIMD on 168
-            // registers, where holding the row samples in vector registers spills
-            // in the recurrence loop: they keep scalar loads of the row samples
-            constexpr bool ROWS_LDS =
-                !(sizeof(F) == 8 && (KIND == AAMP || (KIND == PNORM && PC != P_GENERIC)));
             double *rowst = stage + stage_cols<KD>();   // the chunk's LCH row samples
             double nc[NLD], nr;
             auto fetch = [&](int l0) {
@@ -705,7 +704,7 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
 template <uint32_t SELS, int KD, typename F>
 constexpr int waves_target()
 {
-    if (KD != 8) return 1;
+    if (KD != 8 || (SELS & SEL_LONG)) return 1;
     if (sizeof(F) == 4) return 4;
     return (SELS == SEL_AAMP || SELS == SEL_P1 || SELS == SEL_P3) ? 3 : 1;
 }
@@ -728,6 +727,7 @@ __global__ void __launch_bounds__(64)
     F *rowop = rowbuf + NRB * 64;
     double *stage = lds;
 
+    constexpr bool RL = waves_target<SELS, KD, F>() != 3;
     cint64 *row_base = as_const(b.row_base);
     cint64 *band_start = as_const(b.band_start);
     const int64_t total = row_base[b.njobs];   // band-row positions of the launch
@@ -782,16 +782,16 @@ __global__ void __launch_bounds__(64)
         pos = row0 + i1;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
-            band_item<AAMP, P_TWO, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<AAMP, P_TWO, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
-            band_item<ACAMP, (SELS & SEL_FCMP) ? P_FCMP : P_TWO, KD, F, COUNT>(
+            band_item<ACAMP, (SELS & SEL_FCMP) ? P_FCMP : P_TWO, KD, F, COUNT, RL>(
                 s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_P1) && sel == SEL_P1)
-            band_item<PNORM, P_ONE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<PNORM, P_ONE, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
-            band_item<PNORM, P_THREE, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<PNORM, P_THREE, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_PGEN) && sel == SEL_PGEN)
-            band_item<PNORM, P_GENERIC, KD, F, COUNT>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<PNORM, P_GENERIC, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
     }
 }
 
@@ -866,6 +866,15 @@ const void *band_kernel(uint32_t sels, bool count)
         // the mixed kernel, which visits the same pairs)
         if (sels == (SEL_ACAMP | SEL_FCMP) && !count)
             return (const void *)k_sweep_band<SEL_ACAMP | SEL_FCMP, KD, F, false>;
+        // long windows of the Euclidean and p = 1, 3 distances
+        if ((sels & SEL_LONG) && !count) {
+            switch (sels & SEL_BAND) {
+            case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP | SEL_LONG, KD, F, false>;
+            case SEL_P1: return (const void *)k_sweep_band<SEL_P1 | SEL_LONG, KD, F, false>;
+            case SEL_P3: return (const void *)k_sweep_band<SEL_P3 | SEL_LONG, KD, F, false>;
+            default: break;
+            }
+        }
     }
     if (count) return (const void *)k_sweep_band<SEL_BAND, KD, F, true>;
     switch (sels & SEL_BAND) {

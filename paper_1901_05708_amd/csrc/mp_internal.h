@@ -191,7 +191,15 @@ enum Sel : uint32_t {
     SEL_P3 = 8,
     SEL_PGEN = 16,
     SEL_FCMP = 32,     // a launch flag, not a distance: its ACAMP jobs are keyed on F
+    SEL_LONG = 64,     // a launch flag: FP64 Euclidean / p = 1, 3 jobs with windows of at
+                       // least LONG_WINDOW samples, run at default occupancy with their
+                       // restarts' row samples staged in LDS
 };
+
+// Window length from which FP64 Euclidean and p = 1, 3 sweeps use the
+// SEL_LONG kernels: there the O(m) restarts, not the recurrence, set the time,
+// and the autotuner's grids of one or two waves per SIMD leave registers free.
+constexpr int32_t LONG_WINDOW = 2048;
 
 __host__ __device__ inline uint32_t sel_of(int32_t kind, int32_t pclass)
 {
