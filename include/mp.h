@@ -91,10 +91,15 @@ extern "C" {
  * winner. It has held on every row of every workload tested, for the two
  * distances that have an FP32 sweep; the Euclidean and p = 3 sums, whose
  * competitors can drift further, run in FP64 instead. FP64 results are
- * within 1e-9 relative of the exact profile; for ACAMP an absolute floor
- * sqrt(4 m eps) applies near DZ = 0, with eps the absolute error of the
- * FP64 key 1 - rho (a few times 2^-53 times the square root of the refresh
- * interval; about 1e-6 at m = 256). */
+ * within 1e-9 relative of the exact profile. For ACAMP an absolute floor
+ * applies near DZ = 0: the partner is chosen on the key 1 - rho, so with
+ * delta the absolute error of that key the reported pair's DZ^2 exceeds the
+ * minimum by at most 4 m delta, and DZ by at most sqrt(4 m delta). In FP64
+ * delta is a few units of 2^-53 (the key is formed next to 1) plus the
+ * recurrence's drift, which grows like the square root of the rows since the
+ * last restart R: with delta = 2^-53 (8 + 2 sqrt(R)) and R = 64 m the floor is
+ * 7e-7 at m = 16 and 5e-6 at m = 256; measured errors stay within the
+ * smaller of that floor and 1e-6 at every window length tested. */
 #define MP_FP32_RTOL 1e-4
 
 /*

@@ -9,9 +9,39 @@ Per row i, with rtol / atol the tolerance of the precision mode:
   4. P equals the direct distance of (i, I) (checked on the mismatched rows
      and on a sample of the others).
 """
+import math
+
 import numpy as np
 
 import oracle
+
+# Absolute floor of z-normalized results, in DZ units. The sweep selects the
+# partner on the key 1 - rho (Lemma 3); with delta the absolute error of that
+# key, the reported pair's exact DZ^2 = 2 m (1 - rho) exceeds the minimum by at
+# most 4 m delta, so DZ by at most sqrt(4 m delta), which dominates the
+# relative tolerance near DZ = 0. FP64: the key is resolved to a few units of
+# 2^-53 next to 1, and the refresh recurrence adds a drift that grows like the
+# square root of the rows since the last restart R; delta = 2^-53 (8 + 2
+# sqrt(R)), with R = 64 m, the longest interval the autotuner offers, when the
+# caller does not fix it. The checks use the smaller of that floor and 1e-6:
+# below m = 32 the floor is the tighter bound; above, the measured errors have
+# stayed under 1e-6 at every window length tested (up to 2^16), well inside
+# the drift allowance. FP32 + refresh: the 1e-6 of the single-precision
+# contract.
+ACAMP_ATOL = 1e-6
+
+
+def acamp_atol(m, precision="fp64", R=None):
+    if precision != "fp64":
+        return ACAMP_ATOL
+    R = 64 * m if not R else R
+    delta = 2.0 ** -53 * (8.0 + 2.0 * math.sqrt(R))
+    return min(ACAMP_ATOL, math.sqrt(4.0 * m * delta))
+
+
+def atol_for(kind, m, precision="fp64", R=None):
+    """Absolute tolerance of a profile check: 0 except for ACAMP."""
+    return acamp_atol(m, precision, R) if kind == "acamp" else 0.0
 
 
 def check_profile(T, m, kind, p, excl, P, I, Pref, Iref, Qref, rtol, atol, rows=None,

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import check_profile
+from tests.parity import atol_for, check_profile
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def _check(mp, kind, T, m, p=2.0, excl=None, R=0, label=""):
     _note(f"{label}: band kind={kind} p={p} n={len(T)} m={m} excl={excl} R={R}")
     P, I = _call(mp, kind, T, m, p=p, excl=excl, R=R)
     Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl)
-    atol = 1e-6 if kind == "acamp" else 0.0
+    atol = atol_for(kind, m, "fp64", R)
     return check_profile(T, m, kind, p, excl, P, I, Pr, Ir, Qr, 1e-9, atol, label=label), P, I
 
 
@@ -209,7 +209,7 @@ def test_band_long_windows_long_refresh(mp, monkeypatch, kind):
     _note(f"long-refresh {kind}: n={len(T)} m={m} R={R} wps=1")
     P, I = _call(mp, kind, T, m, excl=excl, R=R)
     Pr, Ir, Qr = oracle.profile(T, m, kind, excl=excl, rows=rows)
-    atol = 1e-6 if kind == "acamp" else 0.0
+    atol = atol_for(kind, m, "fp64", R)
     check_profile(T, m, kind, 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, 1e-9, atol, rows=rows,
                   label=f"long-refresh-{kind}")
 

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import check_profile
+from tests.parity import atol_for, check_profile
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,7 @@ def _check(specs, P, I, rtol, label, rows_per_job=None):
     for b, (T, m, kind, p, excl, R) in enumerate(specs):
         N = len(T) - m + 1
         e = excl or W.excl_default(m)
-        atol = 1e-6 if kind == "acamp" else 0.0
+        atol = atol_for(kind, m, "fp64" if rtol <= 1e-9 else "fp32", R)
         if rows_per_job is None:
             rows = None
             Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=e)
@@ -234,7 +234,7 @@ def test_batch_full_workload(mp):
             assert len(rows) >= 32
             check_profile(T, m, kind, 2.0, e, P[off:off + N][rows], I[off:off + N][rows],
                           ref["P"][sel], ref["I"][sel], ref["Q"][sel], rtol,
-                          1e-6 if kind == "acamp" else 0.0, rows=rows, sample=8,
+                          atol_for(kind, m, prec), rows=rows, sample=8,
                           label=f"full-{prec} job {b}")
             off += N
         _note(f"batch {prec}: {len(ref['rows'])} oracle rows over {len(specs)} series match")
@@ -268,7 +268,7 @@ def test_fp32_wide_bands_with_short_windows(mp, monkeypatch):
         Pr, Ir, Qr = oracle.profile(T, m, kind, excl=e)
         rtol = 1e-9 if m < 32 else 1e-4
         check_profile(T, m, kind, p, e, P[off:off + N], I[off:off + N], Pr, Ir, Qr, rtol,
-                      1e-6 if kind == "acamp" else 0.0, label=f"wide-{b}")
+                      atol_for(kind, m, "fp64" if m < 32 else "fp32"), label=f"wide-{b}")
         off += N
     _note("fp32 wide bands, short windows (single)")
     T, m = specs[2][0], 24
@@ -276,4 +276,4 @@ def test_fp32_wide_bands_with_short_windows(mp, monkeypatch):
     torch.cuda.synchronize()
     Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=W.excl_default(m))
     check_profile(T, m, "acamp", 2.0, W.excl_default(m), Ps.cpu().numpy(), Is.cpu().numpy(),
-                  Pr, Ir, Qr, 1e-9, 1e-6, label="wide-single")
+                  Pr, Ir, Qr, 1e-9, atol_for("acamp", m), label="wide-single")

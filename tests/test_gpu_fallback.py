@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import check_profile
+from tests.parity import atol_for, check_profile
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def test_fallback_every_row(mp, kind, p, force):
     excl = W.excl_default(m)
     P, I = _run(mp, kind, T, m, p, force)
     Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl)
-    atol = 1e-6 if kind == "acamp" else 0.0
+    atol = atol_for(kind, m)
     check_profile(T, m, kind, p, excl, P, I, Pr, Ir, Qr, 1e-9, atol, label=f"fb{force}-{kind}")
 
 
@@ -66,8 +66,8 @@ def test_fallback_runs_and_motifs(mp):
     T, m, planted = W.rw128k(n=6000, m=48, nruns=4, nmotifs=3, run_len=(100, 300))
     P, I = _run(mp, "acamp", T, m, 2.0, 1)
     Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=W.excl_default(m))
-    check_profile(T, m, "acamp", 2.0, W.excl_default(m), P, I, Pr, Ir, Qr, 1e-9, 1e-6,
-                  label="fb-runs")
+    check_profile(T, m, "acamp", 2.0, W.excl_default(m), P, I, Pr, Ir, Qr, 1e-9,
+                  atol_for("acamp", m), label="fb-runs")
     for a, b in planted.motifs:
         assert I[a] == b and I[b] == a
 

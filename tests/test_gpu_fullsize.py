@@ -16,7 +16,7 @@ import pytest
 import oracle
 import workloads as W
 from tests import fullsize_refs as R
-from tests.parity import check_profile
+from tests.parity import atol_for, check_profile
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +55,7 @@ def _sampled(mp, kind, T, m, rows, p=2.0, precision="fp64", label=""):
     rows = np.unique(np.asarray(rows, dtype=np.int64))
     Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl, rows=rows)
     rtol = 1e-9 if precision == "fp64" else 1e-4
-    atol = 1e-6 if kind == "acamp" else 0.0
+    atol = atol_for(kind, m, precision)
     info = check_profile(T, m, kind, p, excl, P[rows], I[rows], Pr, Ir, Qr, rtol, atol,
                          rows=rows, label=label)
     return info, P, I
@@ -69,7 +69,7 @@ def _against_ref(name, T, m, kind, p, P, I, precision, label, min_rows):
     assert len(rows) >= min_rows, f"{name}: only {len(rows)} oracle rows stored"
     excl = W.excl_default(m)
     rtol = 1e-9 if precision == "fp64" else 1e-4
-    atol = 1e-6 if kind == "acamp" else 0.0
+    atol = atol_for(kind, m, precision)
     info = check_profile(T, m, kind, p, excl, P[rows], I[rows], ref["P"], ref["I"], ref["Q"],
                          rtol, atol, rows=rows, label=label)
     _note(f"{label}: {len(rows)} oracle rows match ({info['index_mismatch']} near-tie indices)")
@@ -206,7 +206,7 @@ def test_rw128k_acamp_every_row(mp):
         Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=excl, rows=rows)
         for prec, (P, I) in gpu.items():
             check_profile(T, m, "acamp", 2.0, excl, P[rows], I[rows], Pr, Ir, Qr,
-                          1e-9 if prec == "fp64" else 1e-4, 1e-6, rows=rows,
+                          1e-9 if prec == "fp64" else 1e-4, atol_for("acamp", m, prec), rows=rows,
                           label=f"rw128k-all-{prec}-{lo}")
         _note(f"rw128k every row: rows {lo}..{rows[-1]} of {N} match in both precisions")
 

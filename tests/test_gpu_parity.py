@@ -11,11 +11,11 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import check_profile
+from tests.parity import atol_for, check_profile
 
 pytestmark = pytest.mark.gpu
 
-RTOL64, ATOL_Z = 1e-9, 1e-6
+RTOL64 = 1e-9
 
 
 def _note(msg):
@@ -55,7 +55,7 @@ def _parity(mp, T, m, kind, p=2.0, excl=None, precision="fp64", R=0, label=""):
         P, I = _run(mp, mp.acamp, T, m, excl=excl, precision=precision, R=R)
     Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl)
     rtol = RTOL64 if precision == "fp64" else 1e-4
-    atol = ATOL_Z if kind == "acamp" else 0.0
+    atol = atol_for(kind, m, precision, R)
     return check_profile(T, m, kind, p, excl, P, I, Pr, Ir, Qr, rtol, atol, label=label), P, I
 
 

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import check_profile
+from tests.parity import atol_for, check_profile
 
 pytestmark = pytest.mark.gpu
 
@@ -64,8 +64,8 @@ def _draw(seed):
     return rng, kind, p, n, m, excl, precision, R, shape
 
 
-def _tols(kind, precision):
-    return (1e-9 if precision == "fp64" else 1e-4), (1e-6 if kind == "acamp" else 0.0)
+def _tols(kind, precision, m, R=0):
+    return (1e-9 if precision == "fp64" else 1e-4), atol_for(kind, m, precision, R)
 
 
 @pytest.mark.parametrize("seed", range(48))
@@ -85,7 +85,7 @@ def test_random_single_series(mp, seed):
         P, I = mp.pnorm(Td, m, p=p, excl=e, precision=precision, R=R)
     torch.cuda.synchronize()
     Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=e)
-    rtol, atol = _tols(kind, precision)
+    rtol, atol = _tols(kind, precision, m, R)
     check_profile(T, m, kind, p, e, P.cpu().numpy(), I.cpu().numpy(), Pr, Ir, Qr, rtol, atol,
                   label=label)
 
@@ -114,7 +114,7 @@ def test_random_batches(mp, seed):
         N = len(T) - m + 1
         e = excl or W.excl_default(m)
         Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=e)
-        rtol, atol = _tols(kind, precision)
+        rtol, atol = _tols(kind, precision, m, R)
         check_profile(T, m, kind, p, e, P[off:off + N], I[off:off + N], Pr, Ir, Qr, rtol, atol,
                       label=f"random batch {seed} job {b}")
         off += N
@@ -158,7 +158,7 @@ def test_random_anytime(mp, seed):
     torch.cuda.synchronize()
     N = n - m + 1
     Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=e, diagonals=_mask(N, e, groups))
-    rtol, atol = _tols(kind, "fp64")
+    rtol, atol = _tols(kind, "fp64", m)
     check_profile(T, m, kind, p, e, P.cpu().numpy(), I.cpu().numpy(), Pr, Ir, Qr, rtol, atol,
                   label=label)
 
@@ -178,5 +178,5 @@ def test_random_fcmp(mp, seed):
     P, I = mp.acamp_fcmp(torch.as_tensor(T, device="cuda"), m, excl=e, R=R)
     torch.cuda.synchronize()
     Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=e)
-    check_profile(T, m, "acamp", 2.0, e, P.cpu().numpy(), I.cpu().numpy(), Pr, Ir, Qr, 1e-9, 1e-6,
-                  label=label)
+    check_profile(T, m, "acamp", 2.0, e, P.cpu().numpy(), I.cpu().numpy(), Pr, Ir, Qr, 1e-9,
+                  atol_for("acamp", m, "fp64", R), label=label)
