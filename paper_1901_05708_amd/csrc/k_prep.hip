@@ -15,10 +15,168 @@ namespace mpk {
 constexpr int STATS_BLOCK = 256;   // windows per block of k_window_stats
 constexpr int STATS_CHUNK = 64;    // steps per staged chunk
 
+// ---- long windows: one exact anchor per block, the rest by exact slides ----
+//
+// For m >= LONG_WINDOW the direct two passes cost O(m) per window. A block of
+// 256 windows instead sums its first window (the anchor) exactly and reaches
+// the others by adding what enters and leaves, in double-double arithmetic
+// (an unevaluated sum hi + lo of two doubles, about 106 significant bits;
+// error-free sum and product transformations after Knuth and Dekker; no
+// contraction into fused operations inside them). With
+// every sample shifted by c = t[j0] (u = t - c, rounded once), window j has
+//   S_j = sum u,  Q_j = sum u^2,  mu_j = c + S_j / m,
+//   ||window - mu_j||^2 = (m Q_j - S_j^2) / m,
+// where S_j and Q_j are the anchor's sums plus block-wide prefix sums of
+// u_in - u_out and u_in^2 - u_out^2. The subtraction cancels, but its inputs
+// carry about 2^-104 relative error, so the centred energy keeps about
+// 2^-104 (Q / energy) relative error before its final rounding: far below
+// the two-pass sums' own m 2^-53 for any series whose windows vary above
+// 1e-10 of their offset from c. Constant windows are flagged exactly from
+// integer counts of sample changes, never from the energy.
+struct DD {
+    double hi, lo;
+};
+
+__device__ __forceinline__ DD dd_two_sum(double a, double b)
+{
+#pragma clang fp contract(off)
+    const double s = a + b;
+    const double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ __forceinline__ DD dd_quick(double a, double b)
+{
+#pragma clang fp contract(off)
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ DD dd_add(DD a, DD b)
+{
+#pragma clang fp contract(off)
+    DD s = dd_two_sum(a.hi, b.hi);
+    const DD t = dd_two_sum(a.lo, b.lo);
+    s = dd_quick(s.hi, s.lo + t.hi);
+    return dd_quick(s.hi, s.lo + t.lo);
+}
+
+__device__ __forceinline__ DD dd_prod(double a, double b)
+{
+#pragma clang fp contract(off)
+    const double p = a * b;
+    return {p, fma(a, b, -p)};
+}
+
+__device__ __forceinline__ DD dd_neg(DD a) { return {-a.hi, -a.lo}; }
+
+// Inclusive prefix sums over the block's 256 threads.
+__device__ __forceinline__ DD dd_block_scan(DD v, DD *buf)
+{
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < STATS_BLOCK; off <<= 1) {
+        const DD o = (t >= off) ? buf[t - off] : DD{0.0, 0.0};
+        __syncthreads();
+        v = dd_add(v, o);
+        buf[t] = v;
+        __syncthreads();
+    }
+    return v;
+}
+
+__device__ __forceinline__ int int_block_scan(int v, int *buf)
+{
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < STATS_BLOCK; off <<= 1) {
+        const int o = (t >= off) ? buf[t - off] : 0;
+        __syncthreads();
+        v += o;
+        buf[t] = v;
+        __syncthreads();
+    }
+    return v;
+}
+
+__device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, DD *dbuf,
+                                                  int *ibuf)
+{
+    const int t = threadIdx.x;
+    const gptr<double> T = as_global(s.T);
+    const int64_t tmax = s.n - 1;
+    const int m = s.m;
+    const double c = T[j0];
+    // the anchor window j0: S, Q and the number of sample changes in
+    // (j0, j0 + m - 1], each thread over a stride of the window
+    DD S = {0.0, 0.0}, Q = {0.0, 0.0};
+    int brk = 0;
+    for (int l = t; l < m; l += STATS_BLOCK) {
+        const double v = T[j0 + l];
+        const double u = v - c;
+        S = dd_add(S, {u, 0.0});
+        Q = dd_add(Q, dd_prod(u, u));
+        if (l > 0) brk += (v != T[j0 + l - 1]) ? 1 : 0;
+    }
+    // block totals (the last thread of each inclusive scan holds them)
+    S = dd_block_scan(S, dbuf);
+    const DD S0 = dbuf[STATS_BLOCK - 1];
+    __syncthreads();
+    Q = dd_block_scan(Q, dbuf);
+    const DD Q0 = dbuf[STATS_BLOCK - 1];
+    __syncthreads();
+    brk = int_block_scan(brk, ibuf);
+    const int B0 = ibuf[STATS_BLOCK - 1];
+    __syncthreads();
+    // window j = j0 + t (t >= 1) differs from window j - 1 by u_in = u[j+m-1]
+    // entering and u_out = u[j-1] leaving
+    const int64_t j = j0 + t;
+    DD dS = {0.0, 0.0}, dQ = {0.0, 0.0};
+    int brk_out = 0, brk_in = 0;
+    if (t > 0) {
+        const double vin = T[min(j + m - 1, tmax)], vout = T[j - 1];
+        const double uin = vin - c, uout = vout - c;
+        dS = dd_two_sum(uin, -uout);
+        dQ = dd_add(dd_prod(uin, uin), dd_neg(dd_prod(uout, uout)));
+        // a change at position j (entering the interval (j0, j]) and at j + m - 1
+        brk_out = (T[j] != vout) ? 1 : 0;
+        brk_in = (j + m - 1 <= tmax && vin != T[j + m - 2]) ? 1 : 0;
+    }
+    const DD Sj = dd_add(S0, dd_block_scan(dS, dbuf));
+    __syncthreads();
+    const DD Qj = dd_add(Q0, dd_block_scan(dQ, dbuf));
+    __syncthreads();
+    const int pre = int_block_scan(brk_out, ibuf);
+    __syncthreads();
+    const int post = int_block_scan(brk_in, ibuf);
+    if (j < s.N) {
+        // changes inside (j, j + m - 1]: the anchor's, minus those in (j0, j],
+        // plus those in (j0 + m - 1, j + m - 1]
+        const bool same = (B0 - pre + post) == 0;
+        const double mu = c + (Sj.hi + Sj.lo) / (double)m;
+        const DD mQ = dd_add(dd_prod(Qj.hi, (double)m), dd_prod(Qj.lo, (double)m));
+        const DD S2 = dd_add(dd_prod(Sj.hi, Sj.hi), dd_prod(2.0 * Sj.hi, Sj.lo));
+        const DD e = dd_add(mQ, dd_neg(S2));
+        const double ss = (e.hi + e.lo) / (double)m;
+        s.mu[j] = mu;
+        s.isconst[j] = same ? 1 : 0;
+        s.invn[j] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
+    }
+}
+
 __global__ void __launch_bounds__(STATS_BLOCK) k_window_stats(Batch b)
 {
     const Series s = load_uniform(&b.jobs[blockIdx.y]).s;
     if (s.kind != ACAMP) return;
+    if (s.m >= LONG_WINDOW) {
+        __shared__ DD dbuf[STATS_BLOCK];
+        __shared__ int ibuf[STATS_BLOCK];
+        const int64_t j0 = (int64_t)blockIdx.x * STATS_BLOCK;
+        if (j0 < s.N) window_stats_long(s, j0, dbuf, ibuf);
+        return;
+    }
     // The block's windows j0 .. j0 + 255 need, at step l, the samples
     // t[j0 + l .. j0 + l + 255]: one contiguous run. Chunks of STATS_CHUNK
     // steps are staged in LDS (the next chunk's loads are issued before the

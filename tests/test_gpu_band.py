@@ -214,6 +214,34 @@ def test_band_long_windows_long_refresh(mp, monkeypatch, kind):
                   label=f"long-refresh-{kind}")
 
 
+def test_band_long_windows_runs_offset(mp):
+    """Window statistics of long windows (m >= 2048: one exact anchor per 256
+    windows, the others by exact slides, constant flags from counts of sample
+    changes) on constant runs shorter than, exactly, just over and longer than
+    m, a near-constant run, and an offset of 1e4 against a step scale of 1e-2.
+    Windows inside a run are constant (+inf, -1); rows at every run edge, at
+    every edge minus m, and a sample are checked against the oracle."""
+    rng = np.random.default_rng(77)
+    m, n = 2048, 16000
+    T = 1e4 + 1e-2 * np.cumsum(rng.standard_normal(n))
+    runs = [(1500, 700), (5000, 3000), (9500, 2100), (12500, 2048)]
+    for s0, L in runs:
+        T[s0:s0 + L] = T[s0]
+    T[14700:15600] = T[14700] + 1e-9 * rng.standard_normal(900)
+    excl = W.excl_default(m)
+    N = n - m + 1
+    edges = [e for s0, L in runs for e in (s0, s0 + L)] + [14700, 15600]
+    near = [r for e in edges for base in (e, e - m + 1) for r in range(base - 3, base + 4)]
+    rows = np.unique(np.clip(np.concatenate([near, W.sample_rows(N, 96, 5)]), 0, N - 1))
+    _note(f"long-window stats: acamp n={n} m={m} runs={runs} rows={len(rows)}")
+    P, I = _call(mp, "acamp", T, m, excl=excl)
+    assert np.all(np.isinf(P[5000:5953])) and np.all(I[5000:5953] == -1)
+    assert np.isinf(P[12500]) and np.isfinite(P[12499]) and np.isfinite(P[12501])
+    Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=excl, rows=rows)
+    check_profile(T, m, "acamp", 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, 1e-9,
+                  atol_for("acamp", m), rows=rows, label="long-stats-runs")
+
+
 # ---- p-norms with other p (1 < p <= 6): a band kernel of their own ----
 
 @pytest.mark.parametrize("p", [1.5, 2.5, 4.7, 6.0])
