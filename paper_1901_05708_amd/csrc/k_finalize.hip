@@ -6,6 +6,7 @@
 // precision sweep allows, are queued and searched again exactly: k_fallback_scan
 // scores, straight from the definition, every column that the triangle
 // inequality over a few pivot windows cannot exclude.
+#include "dd.h"
 #include "exact.h"
 #include "keys.h"
 #include "mp_internal.h"
@@ -106,16 +107,17 @@ struct FinLds {
 // together), the winners' samples are a contiguous run too and are staged the
 // same way; otherwise each thread loads its winner's samples. Every exact sum
 // adds its terms in order of l, with the same terms as exact_sum.
+// need / j: whether the block's row i0 + threadIdx.x needs its sum, and the
+// winner (finalize_decode, already applied).
 template <int KIND, int PC>
-__device__ __forceinline__ void finalize_block(const Series &s, const Fallback &fb, int32_t jb,
-                                               int64_t i0, double *P, int64_t *I, FinLds &L)
+__device__ __forceinline__ void finalize_block_sums(const Series &s, const Fallback &fb,
+                                                    int32_t jb, int64_t i0, bool need, int64_t j,
+                                                    double *P, int64_t *I, FinLds &L)
 {
     constexpr int B = FIN_BLOCK, CH = FIN_CHUNK, SPAN = B + CH;
     double *sa = L.sa, *sb = L.sb;
     const int t = threadIdx.x;
     const int64_t i = i0 + t;
-    int64_t j = 0;
-    const bool need = i < s.N && finalize_decode<KIND>(s, fb, jb, i, P, I, &j);
     if (t == 0) {
         L.dlo = INT64_MAX;
         L.dhi = INT64_MIN;
@@ -188,6 +190,205 @@ __device__ __forceinline__ void finalize_block(const Series &s, const Fallback &
     }
 }
 
+template <int KIND, int PC>
+__device__ __forceinline__ void finalize_block(const Series &s, const Fallback &fb, int32_t jb,
+                                               int64_t i0, double *P, int64_t *I, FinLds &L)
+{
+    const int64_t i = i0 + threadIdx.x;
+    int64_t j = 0;
+    const bool need = i < s.N && finalize_decode<KIND>(s, fb, jb, i, P, I, &j);
+    finalize_block_sums<KIND, PC>(s, fb, jb, i0, need, j, P, I, L);
+}
+
+// ---- rescoring of long windows --------------------------------------------
+//
+// For m >= LONG_WINDOW a direct sum per row costs O(m) per row, while
+// neighbouring rows usually have their winners on one diagonal (j = i + d):
+// then the sum of row i follows from that of row i - 1 by adding the term of
+// the pair that enters (i + m - 1, j + m - 1) and subtracting the one that
+// leaves (i - 1, j - 1). A block of 256 rows splits into runs of consecutive
+// rows with a common winner diagonal; the whole block sums each run's first
+// pair over its m terms, and a segmented prefix sum carries it along the run.
+// All of it is double-double (dd.h), so the running sums lose about 2^-104 of
+// their largest partial sum to cancellation instead of 2^-53. The quantities:
+//   AAMP, p-norm: the sum of (a - b)^2 or |a - b|^p (the terms rounded as in
+//     the direct sum, their accumulation exact to double-double);
+//   ACAMP: with the row samples shifted by c_a = t[i0] and the column
+//     samples by c_b = t[j] of the run's first pair (u = t - c, kept exact as
+//     a double-double: rounding it would move rho by 2^-53 times the
+//     window's offset from c over its spread, and 2m (1 - rho) near a perfect
+//     match turns that into an absolute DZ error), the cross sum
+//     C = sum u_a u_b and S, Q = sum u, sum u^2 of both windows; then
+//     m cov = m C - S_a S_b and m ||window - mu||^2 = m Q - S^2, and
+//     DZ^2 = 2m (1 - rho) (Lemma 3) with 1 - rho taken without cancellation:
+//     (E_a E_b - (m cov)^2) / (sqrt(E_a E_b) (sqrt(E_a E_b) + m cov)) for
+//     positive cov, E = m ||window - mu||^2.
+// The rounded result is at least as close to the exact distance as the direct
+// FP64 sum, whose own error grows like m 2^-53.
+constexpr int FL_NQ = 5;   // accumulated quantities per row (ACAMP; 1 otherwise)
+
+struct FinLongLds {
+    DD buf[FIN_BLOCK];
+    long long diag[FIN_BLOCK];
+    int ibuf[FIN_BLOCK];
+    int heads[FIN_BLOCK];
+    double cb[FIN_BLOCK];
+};
+
+// Adds the terms of the pair of samples (a, b) to q.
+template <int KIND, int PC>
+__device__ __forceinline__ void long_terms(DD (&q)[FL_NQ], double a, double b, double ca,
+                                           double cb, double p, double sign)
+{
+    if (KIND == ACAMP) {
+        // the shifted samples exactly (two-sum), their products to 2^-106
+        const DD ua = dd_two_sum(a, -ca), ub = dd_two_sum(b, -cb);
+        const DD sa = (sign < 0.0) ? dd_neg(ua) : ua;   // sign * u_a
+        const DD sb = (sign < 0.0) ? dd_neg(ub) : ub;
+        q[0] = dd_add(q[0], dd_mul(sa, ub));
+        q[1] = dd_add(q[1], sa);
+        q[2] = dd_add(q[2], dd_mul(sa, ua));
+        q[3] = dd_add(q[3], sb);
+        q[4] = dd_add(q[4], dd_mul(sb, ub));
+    } else if (KIND == AAMP) {
+        const double d = a - b;
+        const DD sq = dd_prod(d, d);
+        q[0] = dd_add(q[0], {sign * sq.hi, sign * sq.lo});
+    } else {
+        q[0] = dd_add(q[0], {sign * pn_term<PC>(a - b, p), 0.0});
+    }
+}
+
+// Segmented inclusive prefix sum over the block: a segment starts wherever
+// start is set.
+template <int B>
+__device__ __forceinline__ DD dd_segment_scan(bool start, DD v, DD *buf, int *fbuf)
+{
+    const int t = threadIdx.x;
+    int f = start ? 1 : 0;
+    buf[t] = v;
+    fbuf[t] = f;
+    __syncthreads();
+    for (int off = 1; off < B; off <<= 1) {
+        const DD o = (t >= off) ? buf[t - off] : DD{0.0, 0.0};
+        const int of = (t >= off) ? fbuf[t - off] : 1;
+        __syncthreads();
+        if (!f) {
+            v = dd_add(o, v);
+            f = of;
+        }
+        buf[t] = v;
+        fbuf[t] = f;
+        __syncthreads();
+    }
+    return v;
+}
+
+// A block whose rows split into more runs than this sums every row directly
+// (the anchors are serial within a block; a z-normalized anchor costs about
+// forty times a direct term).
+template <int KIND>
+constexpr int long_runs_max()
+{
+    return KIND == ACAMP ? 8 : 48;
+}
+
+template <int KIND, int PC>
+__device__ __forceinline__ void finalize_block_long(const Series &s, const Fallback &fb,
+                                                    int32_t jb, int64_t i0, double *P,
+                                                    int64_t *I, unsigned char *lds)
+{
+    FinLongLds &L = *reinterpret_cast<FinLongLds *>(lds);
+    constexpr int B = FIN_BLOCK;
+    constexpr int NQ = (KIND == ACAMP) ? FL_NQ : 1;
+    const int t = threadIdx.x;
+    const int64_t i = i0 + t;
+    int64_t j = 0;
+    const bool need = i < s.N && finalize_decode<KIND>(s, fb, jb, i, P, I, &j);
+    const long long dg = need ? (long long)(j - i) : LLONG_MIN;
+    L.diag[t] = dg;
+    __syncthreads();
+    // runs: consecutive rows that need a sum and share the winner diagonal
+    const bool head = need && (t == 0 || L.diag[t - 1] != dg);
+    const int run = int_block_scan<B>(head ? 1 : 0, L.ibuf) - 1;
+    const int nheads = L.ibuf[B - 1];
+    __syncthreads();
+    if (nheads > long_runs_max<KIND>()) {   // block-uniform
+        finalize_block_sums<KIND, PC>(s, fb, jb, i0, need, j, P, I,
+                                      *reinterpret_cast<FinLds *>(lds));
+        return;
+    }
+    if (head) L.heads[run] = t;
+    __syncthreads();
+    const gptr<double> T = as_global(s.T);
+    const int m = s.m;
+    const double p = s.p;
+    const double ca = (KIND == ACAMP) ? T[i0] : 0.0;
+    DD x[FL_NQ];
+#pragma unroll
+    for (int r = 0; r < FL_NQ; ++r) x[r] = {0.0, 0.0};
+    // the first pair of every run, summed by the whole block
+    for (int k = 0; k < nheads; ++k) {
+        const int th = L.heads[k];
+        const int64_t ih = i0 + th, jh = ih + L.diag[th];
+        const double cbk = (KIND == ACAMP) ? T[jh] : 0.0;
+        // two independent partial sums per thread (alternate strides), for
+        // instruction-level parallelism in the serial double-double chains
+        DD q[FL_NQ], q2[FL_NQ];
+#pragma unroll
+        for (int r = 0; r < FL_NQ; ++r) q[r] = q2[r] = {0.0, 0.0};
+        int l = t;
+        for (; l + B < m; l += 2 * B) {
+            long_terms<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
+            long_terms<KIND, PC>(q2, T[ih + l + B], T[jh + l + B], ca, cbk, p, 1.0);
+        }
+        if (l < m) long_terms<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
+#pragma unroll
+        for (int r = 0; r < FL_NQ; ++r) q[r] = dd_add(q[r], q2[r]);
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) {
+            const DD tot = dd_block_sum<B>(q[r], L.buf);
+            if (t == th) x[r] = tot;
+        }
+        if (t == 0) L.cb[k] = cbk;
+    }
+    __syncthreads();
+    // every other row of a run: its pair minus the preceding row's pair
+    if (need && !head) {
+        const double cbr = (KIND == ACAMP) ? L.cb[run] : 0.0;
+        long_terms<KIND, PC>(x, T[i + m - 1], T[j + m - 1], ca, cbr, p, 1.0);
+        long_terms<KIND, PC>(x, T[i - 1], T[j - 1], ca, cbr, p, -1.0);
+    }
+#pragma unroll
+    for (int r = 0; r < NQ; ++r) x[r] = dd_segment_scan<B>(head || !need, x[r], L.buf, L.ibuf);
+    if (!need) return;
+    double ex;
+    if (KIND == ACAMP) {
+        const DD md = {(double)m, 0.0};
+        const DD mcov = dd_sub(dd_mul(md, x[0]), dd_mul(x[1], x[3]));
+        const DD ea = dd_sub(dd_mul(md, x[2]), dd_mul(x[1], x[1]));
+        const DD eb = dd_sub(dd_mul(md, x[4]), dd_mul(x[3], x[3]));
+        const DD eab = dd_mul(ea, eb);
+        const double prod = dd_val(eab);
+        if (!(prod > 0.0)) {
+            ex = exact_sum<KIND, PC>(s, i, j);   // degenerate energies: the direct sum
+        } else {
+            const double sq = sqrt(prod), c = dd_val(mcov);
+            double omr;   // 1 - rho
+            if (c <= 0.0) {
+                omr = 1.0 - c / sq;
+            } else {
+                const DD num = dd_sub(eab, dd_mul(mcov, mcov));
+                omr = fmax(dd_val(num), 0.0) / (sq * (sq + c));
+            }
+            ex = 2.0 * (double)m * omr;
+        }
+    } else {
+        ex = fmax(dd_val(x[0]), 0.0);
+    }
+    finalize_finish<KIND, PC>(s, fb, jb, i, j, ex, P, I);
+}
+
 // Grid: x over blocks of FIN_BLOCK windows, y over jobs.
 __global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Batch b)
 {
@@ -195,7 +396,20 @@ __global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Batch b)
     const Job J = load_uniform(&b.jobs[jb]);
     const int64_t i0 = (int64_t)blockIdx.x * FIN_BLOCK;
     if (i0 >= J.s.N) return;   // block-uniform
-    __shared__ FinLds L;
+    constexpr size_t LDS_BYTES = sizeof(FinLds) > sizeof(FinLongLds) ? sizeof(FinLds)
+                                                                      : sizeof(FinLongLds);
+    __shared__ __align__(16) unsigned char lds[LDS_BYTES];
+    if (J.s.m >= LONG_WINDOW) {
+        switch (sel_of(J.s.kind, J.s.pclass)) {
+        case SEL_AAMP: finalize_block_long<AAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, lds); break;
+        case SEL_ACAMP: finalize_block_long<ACAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, lds); break;
+        case SEL_P1: finalize_block_long<PNORM, P_ONE>(J.s, b.fb, jb, i0, J.P, J.I, lds); break;
+        case SEL_P3: finalize_block_long<PNORM, P_THREE>(J.s, b.fb, jb, i0, J.P, J.I, lds); break;
+        default: finalize_block_long<PNORM, P_GENERIC>(J.s, b.fb, jb, i0, J.P, J.I, lds); break;
+        }
+        return;
+    }
+    FinLds &L = *reinterpret_cast<FinLds *>(lds);
     switch (sel_of(J.s.kind, J.s.pclass)) {
     case SEL_AAMP: finalize_block<AAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
     case SEL_ACAMP: finalize_block<ACAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, L); break;

@@ -1,6 +1,7 @@
 // k_prep.hip -- per-window preparation that sits outside the sweep's inner
 // loop: the O(m (n - m)) part of the method (Secs. 3.3 and 4.3), computed once
 // per window in FP64 instead of once per diagonal.
+#include "dd.h"
 #include "keys.h"
 #include "mp_internal.h"
 
@@ -20,10 +21,8 @@ constexpr int STATS_CHUNK = 64;    // steps per staged chunk
 // For m >= LONG_WINDOW the direct two passes cost O(m) per window. A block of
 // 256 windows instead sums its first window (the anchor) exactly and reaches
 // the others by adding what enters and leaves, in double-double arithmetic
-// (an unevaluated sum hi + lo of two doubles, about 106 significant bits;
-// error-free sum and product transformations after Knuth and Dekker; no
-// contraction into fused operations inside them). With
-// every sample shifted by c = t[j0] (u = t - c, rounded once), window j has
+// (dd.h). With every sample shifted by c = t[j0] (u = t - c, kept exact as a
+// double-double), window j has
 //   S_j = sum u,  Q_j = sum u^2,  mu_j = c + S_j / m,
 //   ||window - mu_j||^2 = (m Q_j - S_j^2) / m,
 // where S_j and Q_j are the anchor's sums plus block-wide prefix sums of
@@ -33,74 +32,6 @@ constexpr int STATS_CHUNK = 64;    // steps per staged chunk
 // the two-pass sums' own m 2^-53 for any series whose windows vary above
 // 1e-10 of their offset from c. Constant windows are flagged exactly from
 // integer counts of sample changes, never from the energy.
-struct DD {
-    double hi, lo;
-};
-
-__device__ __forceinline__ DD dd_two_sum(double a, double b)
-{
-#pragma clang fp contract(off)
-    const double s = a + b;
-    const double bb = s - a;
-    return {s, (a - (s - bb)) + (b - bb)};
-}
-
-__device__ __forceinline__ DD dd_quick(double a, double b)
-{
-#pragma clang fp contract(off)
-    const double s = a + b;
-    return {s, b - (s - a)};
-}
-
-__device__ __forceinline__ DD dd_add(DD a, DD b)
-{
-#pragma clang fp contract(off)
-    DD s = dd_two_sum(a.hi, b.hi);
-    const DD t = dd_two_sum(a.lo, b.lo);
-    s = dd_quick(s.hi, s.lo + t.hi);
-    return dd_quick(s.hi, s.lo + t.lo);
-}
-
-__device__ __forceinline__ DD dd_prod(double a, double b)
-{
-#pragma clang fp contract(off)
-    const double p = a * b;
-    return {p, fma(a, b, -p)};
-}
-
-__device__ __forceinline__ DD dd_neg(DD a) { return {-a.hi, -a.lo}; }
-
-// Inclusive prefix sums over the block's 256 threads.
-__device__ __forceinline__ DD dd_block_scan(DD v, DD *buf)
-{
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < STATS_BLOCK; off <<= 1) {
-        const DD o = (t >= off) ? buf[t - off] : DD{0.0, 0.0};
-        __syncthreads();
-        v = dd_add(v, o);
-        buf[t] = v;
-        __syncthreads();
-    }
-    return v;
-}
-
-__device__ __forceinline__ int int_block_scan(int v, int *buf)
-{
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < STATS_BLOCK; off <<= 1) {
-        const int o = (t >= off) ? buf[t - off] : 0;
-        __syncthreads();
-        v += o;
-        buf[t] = v;
-        __syncthreads();
-    }
-    return v;
-}
-
 __device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, DD *dbuf,
                                                   int *ibuf)
 {
@@ -115,19 +46,15 @@ __device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, D
     int brk = 0;
     for (int l = t; l < m; l += STATS_BLOCK) {
         const double v = T[j0 + l];
-        const double u = v - c;
-        S = dd_add(S, {u, 0.0});
-        Q = dd_add(Q, dd_prod(u, u));
+        const DD u = dd_two_sum(v, -c);
+        S = dd_add(S, u);
+        Q = dd_add(Q, dd_mul(u, u));
         if (l > 0) brk += (v != T[j0 + l - 1]) ? 1 : 0;
     }
     // block totals (the last thread of each inclusive scan holds them)
-    S = dd_block_scan(S, dbuf);
-    const DD S0 = dbuf[STATS_BLOCK - 1];
-    __syncthreads();
-    Q = dd_block_scan(Q, dbuf);
-    const DD Q0 = dbuf[STATS_BLOCK - 1];
-    __syncthreads();
-    brk = int_block_scan(brk, ibuf);
+    const DD S0 = dd_block_sum<STATS_BLOCK>(S, dbuf);
+    const DD Q0 = dd_block_sum<STATS_BLOCK>(Q, dbuf);
+    brk = int_block_scan<STATS_BLOCK>(brk, ibuf);
     const int B0 = ibuf[STATS_BLOCK - 1];
     __syncthreads();
     // window j = j0 + t (t >= 1) differs from window j - 1 by u_in = u[j+m-1]
@@ -137,20 +64,20 @@ __device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, D
     int brk_out = 0, brk_in = 0;
     if (t > 0) {
         const double vin = T[min(j + m - 1, tmax)], vout = T[j - 1];
-        const double uin = vin - c, uout = vout - c;
-        dS = dd_two_sum(uin, -uout);
-        dQ = dd_add(dd_prod(uin, uin), dd_neg(dd_prod(uout, uout)));
+        const DD uin = dd_two_sum(vin, -c), uout = dd_two_sum(vout, -c);
+        dS = dd_sub(uin, uout);
+        dQ = dd_sub(dd_mul(uin, uin), dd_mul(uout, uout));
         // a change at position j (entering the interval (j0, j]) and at j + m - 1
         brk_out = (T[j] != vout) ? 1 : 0;
         brk_in = (j + m - 1 <= tmax && vin != T[j + m - 2]) ? 1 : 0;
     }
-    const DD Sj = dd_add(S0, dd_block_scan(dS, dbuf));
+    const DD Sj = dd_add(S0, dd_block_scan<STATS_BLOCK>(dS, dbuf));
     __syncthreads();
-    const DD Qj = dd_add(Q0, dd_block_scan(dQ, dbuf));
+    const DD Qj = dd_add(Q0, dd_block_scan<STATS_BLOCK>(dQ, dbuf));
     __syncthreads();
-    const int pre = int_block_scan(brk_out, ibuf);
+    const int pre = int_block_scan<STATS_BLOCK>(brk_out, ibuf);
     __syncthreads();
-    const int post = int_block_scan(brk_in, ibuf);
+    const int post = int_block_scan<STATS_BLOCK>(brk_in, ibuf);
     if (j < s.N) {
         // changes inside (j, j + m - 1]: the anchor's, minus those in (j0, j],
         // plus those in (j0 + m - 1, j + m - 1]

@@ -215,15 +215,20 @@ def test_band_long_windows_long_refresh(mp, monkeypatch, kind):
 
 
 def test_band_long_windows_runs_offset(mp):
-    """Window statistics of long windows (m >= 2048: one exact anchor per 256
-    windows, the others by exact slides, constant flags from counts of sample
-    changes) on constant runs shorter than, exactly, just over and longer than
-    m, a near-constant run, and an offset of 1e4 against a step scale of 1e-2.
+    """Window statistics and rescoring of long windows (m >= 2048: one exact
+    anchor per 256 windows and exact slides, constant flags from counts of
+    sample changes; winners summed once per run of a common diagonal) on
+    constant runs shorter than, exactly, just over and longer than m and a
+    near-constant run; then on a walk offset by 1e4 with steps of 1e-2.
     Windows inside a run are constant (+inf, -1); rows at every run edge, at
-    every edge minus m, and a sample are checked against the oracle."""
+    every edge minus m, and a sample are checked against the oracle. (The
+    windows that end a run's approach hold one walk sample and m - 1 equal
+    ones; pairs of them match exactly, DZ = 0, and on an offset series the
+    oracle's FP64 means put its own value of such a pair microunits off, so
+    the two cases are separate.)"""
     rng = np.random.default_rng(77)
     m, n = 2048, 16000
-    T = 1e4 + 1e-2 * np.cumsum(rng.standard_normal(n))
+    T = np.cumsum(rng.standard_normal(n))
     runs = [(1500, 700), (5000, 3000), (9500, 2100), (12500, 2048)]
     for s0, L in runs:
         T[s0:s0 + L] = T[s0]
@@ -240,6 +245,14 @@ def test_band_long_windows_runs_offset(mp):
     Pr, Ir, Qr = oracle.profile(T, m, "acamp", excl=excl, rows=rows)
     check_profile(T, m, "acamp", 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, 1e-9,
                   atol_for("acamp", m), rows=rows, label="long-stats-runs")
+    To = 1e4 + 1e-2 * np.cumsum(np.random.default_rng(78).standard_normal(n))
+    rows = W.sample_rows(N, 128, 6)
+    _note(f"long-window stats: acamp offset 1e4 n={n} m={m} rows={len(rows)}")
+    for kind in ("acamp", "aamp"):
+        P, I = _call(mp, kind, To, m, excl=excl)
+        Pr, Ir, Qr = oracle.profile(To, m, kind, excl=excl, rows=rows)
+        check_profile(To, m, kind, 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, 1e-9,
+                      atol_for(kind, m), rows=rows, label=f"long-offset-{kind}")
 
 
 # ---- p-norms with other p (1 < p <= 6): a band kernel of their own ----
