@@ -102,6 +102,31 @@ __device__ __forceinline__ int int_block_scan(int v, int *buf)
     return v;
 }
 
+// Segmented inclusive prefix sums over a block of B threads: a segment
+// starts wherever start is set (fbuf[B] holds the flags).
+template <int B>
+__device__ __forceinline__ DD dd_segment_scan(bool start, DD v, DD *buf, int *fbuf)
+{
+    const int t = threadIdx.x;
+    int f = start ? 1 : 0;
+    buf[t] = v;
+    fbuf[t] = f;
+    __syncthreads();
+    for (int off = 1; off < B; off <<= 1) {
+        const DD o = (t >= off) ? buf[t - off] : DD{0.0, 0.0};
+        const int of = (t >= off) ? fbuf[t - off] : 1;
+        __syncthreads();
+        if (!f) {
+            v = dd_add(o, v);
+            f = of;
+        }
+        buf[t] = v;
+        fbuf[t] = f;
+        __syncthreads();
+    }
+    return v;
+}
+
 // Block-wide sum, returned to every thread.
 template <int B>
 __device__ __forceinline__ DD dd_block_sum(DD v, DD *buf)

@@ -259,31 +259,6 @@ __device__ __forceinline__ void long_terms(DD (&q)[FL_NQ], double a, double b, d
     }
 }
 
-// Segmented inclusive prefix sum over the block: a segment starts wherever
-// start is set.
-template <int B>
-__device__ __forceinline__ DD dd_segment_scan(bool start, DD v, DD *buf, int *fbuf)
-{
-    const int t = threadIdx.x;
-    int f = start ? 1 : 0;
-    buf[t] = v;
-    fbuf[t] = f;
-    __syncthreads();
-    for (int off = 1; off < B; off <<= 1) {
-        const DD o = (t >= off) ? buf[t - off] : DD{0.0, 0.0};
-        const int of = (t >= off) ? fbuf[t - off] : 1;
-        __syncthreads();
-        if (!f) {
-            v = dd_add(o, v);
-            f = of;
-        }
-        buf[t] = v;
-        fbuf[t] = f;
-        __syncthreads();
-    }
-    return v;
-}
-
 // A block whose rows split into more runs than this sums every row directly
 // (the anchors are serial within a block; a z-normalized anchor costs about
 // forty times a direct term).

@@ -9,10 +9,11 @@ namespace mpk {
 
 // Window mean, exact all-equal flag and inverse centred norm
 // invn_j = 1 / sqrt(sum_l (t_{j+l} - mu_j)^2) = 1 / (sqrt(m) sigma_j) with the
-// population standard deviation of App. A, computed directly in two passes per
-// window (no running sums, so no cancellation over long series). A constant
-// window gets invn = 0; its z-normalized distance to anything is infinite
-// (Sec. 1) and the sweep never lets it win.
+// population standard deviation of App. A. Below LONG_WINDOW they are computed
+// directly in two passes per window (no running sums, so no cancellation over
+// long series); from LONG_WINDOW on, by exact slides from one anchor per block
+// (below). A constant window gets invn = 0; its z-normalized distance to
+// anything is infinite (Sec. 1) and the sweep never lets it win.
 constexpr int STATS_BLOCK = 256;   // windows per block of k_window_stats
 constexpr int STATS_CHUNK = 64;    // steps per staged chunk
 
@@ -82,11 +83,9 @@ __device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, D
         // changes inside (j, j + m - 1]: the anchor's, minus those in (j0, j],
         // plus those in (j0 + m - 1, j + m - 1]
         const bool same = (B0 - pre + post) == 0;
-        const double mu = c + (Sj.hi + Sj.lo) / (double)m;
-        const DD mQ = dd_add(dd_prod(Qj.hi, (double)m), dd_prod(Qj.lo, (double)m));
-        const DD S2 = dd_add(dd_prod(Sj.hi, Sj.hi), dd_prod(2.0 * Sj.hi, Sj.lo));
-        const DD e = dd_add(mQ, dd_neg(S2));
-        const double ss = (e.hi + e.lo) / (double)m;
+        const double mu = c + dd_val(Sj) / (double)m;
+        const DD e = dd_sub(dd_mul(Qj, {(double)m, 0.0}), dd_mul(Sj, Sj));   // m ||w - mu||^2
+        const double ss = dd_val(e) / (double)m;
         s.mu[j] = mu;
         s.isconst[j] = same ? 1 : 0;
         s.invn[j] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
