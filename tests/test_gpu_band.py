@@ -195,6 +195,15 @@ def test_band_long_windows_pnorm(mp):
     _check(mp, "pnorm", T, 2048, p=1.0, label="long-p1")
 
 
+def test_band_long_windows_pnorm_generic_fp32(mp):
+    """The long-window rescoring of p-norms: a non-integer p (its terms are
+    powers, rounded as in the direct sum) on an offset series, and p = 1 in
+    FP32 + refresh, whose self-check compares the carried sums."""
+    T, _ = W.sines(n=5000, m=2048)
+    _check(mp, "pnorm", T + 300.0, 2048, p=2.5, label="long-pgen-offset")
+    _check32(mp, "pnorm", T, 2048, p=1.0, label="long-fp32-p1")
+
+
 @pytest.mark.parametrize("kind", ["aamp", "acamp"])
 def test_band_long_windows_long_refresh(mp, monkeypatch, kind):
     """m = 2048 over 20000 samples with the longest refresh interval the

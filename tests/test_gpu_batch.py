@@ -114,6 +114,28 @@ def test_batch_single_kind_kernels(mp):
         _check(specs, P, I, 1e-9, f"single-{kind}{p}")
 
 
+def test_batch_long_and_short_windows(mp):
+    """One launch holding windows on both sides of the long-window limit
+    (2048): the statistics and the rescoring take the anchored path for some
+    jobs and the direct one for others, per job. Both precisions, sampled
+    rows of every job against the oracle."""
+    rng = np.random.default_rng(4242)
+    specs = []
+    for k, (m, kind, p) in enumerate([(2100, "acamp", 2.0), (64, "acamp", 2.0), (3000, "aamp", 2.0),
+                                      (200, "aamp", 2.0), (2048, "pnorm", 3.0), (2500, "acamp", 2.0),
+                                      (100, "pnorm", 1.0)]):
+        n = m + int(rng.integers(3000, 7000))
+        T = np.cumsum(rng.standard_normal(n))
+        if k == 5:
+            T[1000:1000 + 2600] = T[1000]   # a constant run longer than m
+        specs.append((T, m, kind, p, 0, 0))
+    for prec, rtol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        _note(f"batch long+short windows {prec}: " +
+              ", ".join(f"{kd} m={m} n={len(T)}" for T, m, kd, p, e, R in specs))
+        P, I, _ = _run(mp, specs, precision=prec)
+        _check(specs, P, I, rtol, f"long-short-{prec}", rows_per_job=160)
+
+
 def test_batch_matches_single_series_calls(mp):
     import torch
     specs = _mixed_specs(3, 8, 3000, BAND, with_runs=False)
