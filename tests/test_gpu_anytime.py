@@ -127,6 +127,32 @@ def test_resume_gives_the_union(mp, kind):
     assert torch.equal(P, P_ab) and torch.equal(I, I_ab)
 
 
+@pytest.mark.parametrize("kind", ["acamp", "aamp"])
+def test_long_windows_groups_and_resume(mp, kind):
+    """m = 2048: the partial sweep's rows go through the long-window
+    statistics and rescoring (anchors per run of a common winner diagonal);
+    rows with no candidate on the called groups stay +inf. Two calls, then
+    the union, on sampled rows and on the rows around the constant runs."""
+    import torch
+    n, m = 12000, 2048
+    excl = W.excl_default(m)
+    T = _series(21, n, kind)
+    N = n - m + 1
+    G = mp.anytime_groups(n, m, excl)
+    A, B = [0, 2, G - 1], [1, 5]
+    rows = np.unique(np.concatenate([W.sample_rows(N, 96, 8),
+                                     np.arange(n // 3 - m - 3, n // 3 + 5),
+                                     np.arange(2 * n // 3 - 5, 2 * n // 3 + 5)]))
+    rows = rows[(rows >= 0) & (rows < N)]
+    Td = torch.as_tensor(T, device="cuda")
+    _note(f"anytime long windows {kind} n={n} m={m} groups A={A} B={B}")
+    P, I = mp.anytime(Td, m, A, kind=kind, excl=excl)
+    _check(T, m, kind, 2.0, excl, P, I, A, f"any-long-A-{kind}", rows=rows)
+    mp.anytime(Td, m, B, kind=kind, excl=excl, P=P, I=I)
+    _check(T, m, kind, 2.0, excl, P, I, sorted(set(A) | set(B)), f"any-long-AB-{kind}",
+           rows=rows)
+
+
 def test_all_groups_give_the_full_profile(mp):
     import torch
     n, m = 7000, 50
