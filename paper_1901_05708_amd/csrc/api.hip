@@ -452,15 +452,19 @@ int32_t default_R(uint32_t sel, bool fp32, int32_t m)
 // Where a band's exact restart goes in the split of the row space: a band of
 // L rows takes band_cost + L positions, so that a wave whose share holds many
 // short bands (the end of every triangle) is not left with all their
-// restarts. The restart costs about m FMAs per diagonal against about 8 VALU
-// operations per pair and row in the sweep (Euclidean, z-normalized; the
-// p-norm restarts take 2-4 operations per sample, and for other p one pow
-// per sample against two per pair).
+// restarts. By instruction count a restart of m samples costs about m / 6
+// rows of the sweep (about 11 VALU operations per sample and lane against 71
+// per row, Euclidean and z-normalized), but it runs at a lower issue rate;
+// measured over m / 8 ... m / 3 on the long windows of the uniform series,
+// m / 4 balanced the waves best (m = 16384: 2800 -> 3215 G pairs/s, m = 65536:
+// 1455 -> 1575, both Euclidean, against m / 8), with the headline unchanged.
+// The p-norm restarts take 2-4 operations per sample, and for other p one pow
+// per sample against two per pair, so they are charged in proportion.
 int32_t band_cost(uint32_t sel, int32_t m)
 {
-    if (sel == SEL_PGEN) return (m + 1) / 2;
+    if (sel == SEL_PGEN) return m;
     const bool pnorm = sel == SEL_P1 || sel == SEL_P3;
-    return pnorm ? (m + 3) / 4 : (m + 7) / 8;
+    return pnorm ? (m + 1) / 2 : (m + 3) / 4;
 }
 
 // Rows summed over all bands (band b: N - excl - b W rows) and the band count.
