@@ -44,6 +44,24 @@ __device__ __forceinline__ DD dd_add(DD a, DD b)
     return dd_quick(s.hi, s.lo + t.lo);
 }
 
+// q += v for a running sum q of many terms: the rounding error of the high
+// parts' sum goes to q.lo exactly (two-sum), and v.lo is added to q.lo in
+// plain precision. q.lo is not renormalised after each term, so it collects
+// the errors of all terms; its own rounding is 2^-53 of that collected error,
+// which leaves the sum with an error of order 2^-106 times the sum of the
+// terms' magnitudes, as in an ordinary double-double sum (the twice-the-
+// working-precision summation of Ogita, Rump and Oishi). dd_norm restores
+// |lo| <= ulp(hi) / 2 before q is used as a double-double.
+__device__ __forceinline__ void dd_acc(DD &q, DD v)
+{
+#pragma clang fp contract(off)
+    const DD s = dd_two_sum(q.hi, v.hi);
+    q.hi = s.hi;
+    q.lo += s.lo + v.lo;
+}
+
+__device__ __forceinline__ DD dd_norm(DD q) { return dd_two_sum(q.hi, q.lo); }
+
 __device__ __forceinline__ DD dd_neg(DD a) { return {-a.hi, -a.lo}; }
 
 __device__ __forceinline__ DD dd_sub(DD a, DD b) { return dd_add(a, dd_neg(b)); }

@@ -235,7 +235,8 @@ struct FinLongLds {
     double cb[FIN_BLOCK];
 };
 
-// Adds the terms of the pair of samples (a, b) to q.
+// Adds the terms of the pair of samples (a, b) to the running sums q
+// (unnormalised: dd_norm them before other double-double arithmetic).
 template <int KIND, int PC>
 __device__ __forceinline__ void long_terms(DD (&q)[FL_NQ], double a, double b, double ca,
                                            double cb, double p, double sign)
@@ -245,27 +246,28 @@ __device__ __forceinline__ void long_terms(DD (&q)[FL_NQ], double a, double b, d
         const DD ua = dd_two_sum(a, -ca), ub = dd_two_sum(b, -cb);
         const DD sa = (sign < 0.0) ? dd_neg(ua) : ua;   // sign * u_a
         const DD sb = (sign < 0.0) ? dd_neg(ub) : ub;
-        q[0] = dd_add(q[0], dd_mul(sa, ub));
-        q[1] = dd_add(q[1], sa);
-        q[2] = dd_add(q[2], dd_mul(sa, ua));
-        q[3] = dd_add(q[3], sb);
-        q[4] = dd_add(q[4], dd_mul(sb, ub));
+        dd_acc(q[0], dd_mul(sa, ub));
+        dd_acc(q[1], sa);
+        dd_acc(q[2], dd_mul(sa, ua));
+        dd_acc(q[3], sb);
+        dd_acc(q[4], dd_mul(sb, ub));
     } else if (KIND == AAMP) {
         const double d = a - b;
         const DD sq = dd_prod(d, d);
-        q[0] = dd_add(q[0], {sign * sq.hi, sign * sq.lo});
+        dd_acc(q[0], {sign * sq.hi, sign * sq.lo});
     } else {
-        q[0] = dd_add(q[0], {sign * pn_term<PC>(a - b, p), 0.0});
+        dd_acc(q[0], {sign * pn_term<PC>(a - b, p), 0.0});
     }
 }
 
 // A block whose rows split into more runs than this sums every row directly
-// (the anchors are serial within a block; a z-normalized anchor costs about
-// forty times a direct term).
+// (the anchors are serial within a block; a z-normalized anchor term costs
+// about twenty direct terms). For z-normalized pairs 16 timed best of 8, 16
+// and 32 runs on the uniform series at m = 16384 and 65536.
 template <int KIND>
 constexpr int long_runs_max()
 {
-    return KIND == ACAMP ? 8 : 48;
+    return KIND == ACAMP ? 16 : 48;
 }
 
 template <int KIND, int PC>
@@ -319,7 +321,7 @@ __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallb
         }
         if (l < m) long_terms<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
 #pragma unroll
-        for (int r = 0; r < FL_NQ; ++r) q[r] = dd_add(q[r], q2[r]);
+        for (int r = 0; r < FL_NQ; ++r) q[r] = dd_add(dd_norm(q[r]), dd_norm(q2[r]));
 #pragma unroll
         for (int r = 0; r < NQ; ++r) {
             const DD tot = dd_block_sum<B>(q[r], L.buf);
@@ -333,6 +335,8 @@ __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallb
         const double cbr = (KIND == ACAMP) ? L.cb[run] : 0.0;
         long_terms<KIND, PC>(x, T[i + m - 1], T[j + m - 1], ca, cbr, p, 1.0);
         long_terms<KIND, PC>(x, T[i - 1], T[j - 1], ca, cbr, p, -1.0);
+#pragma unroll
+        for (int r = 0; r < NQ; ++r) x[r] = dd_norm(x[r]);
     }
 #pragma unroll
     for (int r = 0; r < NQ; ++r) x[r] = dd_segment_scan<B>(head || !need, x[r], L.buf, L.ibuf);
