@@ -926,11 +926,13 @@ int record(hipEvent_t e, hipStream_t s)
     return MP_OK;
 }
 
-// The faster of two timed runs of a candidate (after a first, warming run)
-// on stream ls; candidates within a few percent of each other otherwise swap
-// places from call to call. A candidate whose first run already takes 1.5
-// times the best time so far (best >= 0) is not run again: its first time
-// is reported.
+// The slower of two timed runs of a candidate (after a first, warming run)
+// on stream ls. Grids of one or two waves per SIMD can run either at full
+// speed or about 1.4 times slower from one launch to the next (the same grid
+// measured 9.2 and 13.4 ms on long windows), so a candidate counts as fast
+// only if both of its runs are; its faster run alone would let such a grid
+// win on a lucky trial and then run slow. A candidate whose first run already takes 1.5 times the
+// best time so far (best >= 0) is not run again: its first time is reported.
 int time_candidate(const std::vector<Spec> &specs, int32_t precision, const Tuning &tu,
                    Workspace &w, hipStream_t ls, hipEvent_t e0, hipEvent_t e1, float best,
                    float *ms)
@@ -957,7 +959,7 @@ int time_candidate(const std::vector<Spec> &specs, int32_t precision, const Tuni
         if (hopeless) *ms = first;
         for (int rep = 0; rep < 2 && !rc && !hopeless; ++rep) {
             float tr = 0.0f;
-            if (!(rc = timed_run(&tr)) && (rep == 0 || tr < *ms)) *ms = tr;
+            if (!(rc = timed_run(&tr)) && (rep == 0 || tr > *ms)) *ms = tr;
         }
         hipError_t es = hipStreamSynchronize(ls);
         if (!rc && es != hipSuccess) rc = fail_hip(es, "autotune");
