@@ -214,18 +214,23 @@ __device__ __forceinline__ void finalize_block(const Series &s, const Fallback &
 //   AAMP, p-norm: the sum of (a - b)^2 or |a - b|^p (the terms rounded as in
 //     the direct sum, their accumulation exact to double-double);
 //   ACAMP: with the row samples shifted by c_a = t[i0] and the column
-//     samples by c_b = t[j] of the run's first pair (u = t - c, kept exact as
-//     a double-double: rounding it would move rho by 2^-53 times the
-//     window's offset from c over its spread, and 2m (1 - rho) near a perfect
-//     match turns that into an absolute DZ error), the cross sum
-//     C = sum u_a u_b and S, Q = sum u, sum u^2 of both windows; then
-//     m cov = m C - S_a S_b and m ||window - mu||^2 = m Q - S^2, and
+//     samples by c_b, the first sample of the 256-window block of the run's
+//     first column window (u = t - c, kept exact as a double-double: rounding
+//     it would move rho by 2^-53 times the window's offset from c over its
+//     spread, and 2m (1 - rho) near a perfect match turns that into an
+//     absolute DZ error), the cross sum C = sum u_a u_b. The window sums
+//     S = sum u and Q = sum u^2 come from the window statistics (k_prep keeps
+//     them, double-double, shifted by the first sample of each window's
+//     256-window block: c_a for the rows of this block, moved to c_b for the
+//     column windows by S(c_b) = S(c) + m (c - c_b)). Then
+//     m cov = m C - S_a S_b and E = m ||window - mu||^2 = m Q - S^2 (both the
+//     same for any shifts, as long as C, S_a and S_b share them), and
 //     DZ^2 = 2m (1 - rho) (Lemma 3) with 1 - rho taken without cancellation:
 //     (E_a E_b - (m cov)^2) / (sqrt(E_a E_b) (sqrt(E_a E_b) + m cov)) for
-//     positive cov, E = m ||window - mu||^2.
+//     positive cov.
 // The rounded result is at least as close to the exact distance as the direct
 // FP64 sum, whose own error grows like m 2^-53.
-constexpr int FL_NQ = 5;   // accumulated quantities per row (ACAMP; 1 otherwise)
+static_assert(FIN_BLOCK == 256, "the rescoring's row shift is the window statistics' block shift");
 
 struct FinLongLds {
     DD buf[FIN_BLOCK];
@@ -235,40 +240,37 @@ struct FinLongLds {
     double cb[FIN_BLOCK];
 };
 
-// Adds the terms of the pair of samples (a, b) to the running sums q
-// (unnormalised: dd_norm them before other double-double arithmetic).
+// Adds the term of the pair of samples (a, b) to the running sum q
+// (unnormalised: dd_norm it before other double-double arithmetic).
 template <int KIND, int PC>
-__device__ __forceinline__ void long_terms(DD (&q)[FL_NQ], double a, double b, double ca,
-                                           double cb, double p, double sign)
+__device__ __forceinline__ void long_term(DD &q, double a, double b, double ca, double cb,
+                                          double p, double sign)
 {
     if (KIND == ACAMP) {
-        // the shifted samples exactly (two-sum), their products to 2^-106
+        // the shifted samples exactly (two-sum), their product to 2^-106
         const DD ua = dd_two_sum(a, -ca), ub = dd_two_sum(b, -cb);
-        const DD sa = (sign < 0.0) ? dd_neg(ua) : ua;   // sign * u_a
-        const DD sb = (sign < 0.0) ? dd_neg(ub) : ub;
-        dd_acc(q[0], dd_mul(sa, ub));
-        dd_acc(q[1], sa);
-        dd_acc(q[2], dd_mul(sa, ua));
-        dd_acc(q[3], sb);
-        dd_acc(q[4], dd_mul(sb, ub));
+        dd_acc(q, dd_mul((sign < 0.0) ? dd_neg(ua) : ua, ub));
     } else if (KIND == AAMP) {
         const double d = a - b;
         const DD sq = dd_prod(d, d);
-        dd_acc(q[0], {sign * sq.hi, sign * sq.lo});
+        dd_acc(q, {sign * sq.hi, sign * sq.lo});
     } else {
-        dd_acc(q[0], {sign * pn_term<PC>(a - b, p), 0.0});
+        dd_acc(q, {sign * pn_term<PC>(a - b, p), 0.0});
     }
 }
 
-// A block whose rows split into more runs than this sums every row directly
-// (the anchors are serial within a block; a z-normalized anchor term costs
-// about twenty direct terms). For z-normalized pairs 16 timed best of 8, 16
-// and 32 runs on the uniform series at m = 16384 and 65536.
-template <int KIND>
-constexpr int long_runs_max()
+// The shift of window j's sums in wsum: the first sample of its block.
+__device__ __forceinline__ double wsum_shift(const gptr<double> T, int64_t j)
 {
-    return KIND == ACAMP ? 16 : 48;
+    return T[j & ~(int64_t)(FIN_BLOCK - 1)];
 }
+
+// A block whose rows split into more runs than this sums every row directly
+// (the anchors are serial within a block). Thresholds of 1-96 timed within
+// noise of 48 for the Euclidean distance; for z-normalized pairs 48 timed
+// best of 16, 32 and 48 at m = 16384 and 65536 (runs of at most 48 cover
+// nearly every block of the uniform series there).
+constexpr int LONG_RUNS_MAX = 48;
 
 template <int KIND, int PC>
 __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallback &fb,
@@ -277,7 +279,6 @@ __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallb
 {
     FinLongLds &L = *reinterpret_cast<FinLongLds *>(lds);
     constexpr int B = FIN_BLOCK;
-    constexpr int NQ = (KIND == ACAMP) ? FL_NQ : 1;
     const int t = threadIdx.x;
     const int64_t i = i0 + t;
     int64_t j = 0;
@@ -290,7 +291,7 @@ __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallb
     const int run = int_block_scan<B>(head ? 1 : 0, L.ibuf) - 1;
     const int nheads = L.ibuf[B - 1];
     __syncthreads();
-    if (nheads > long_runs_max<KIND>()) {   // block-uniform
+    if (nheads > LONG_RUNS_MAX) {   // block-uniform
         finalize_block_sums<KIND, PC>(s, fb, jb, i0, need, j, P, I,
                                       *reinterpret_cast<FinLds *>(lds));
         return;
@@ -301,52 +302,47 @@ __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallb
     const int m = s.m;
     const double p = s.p;
     const double ca = (KIND == ACAMP) ? T[i0] : 0.0;
-    DD x[FL_NQ];
-#pragma unroll
-    for (int r = 0; r < FL_NQ; ++r) x[r] = {0.0, 0.0};
+    DD x = {0.0, 0.0};
     // the first pair of every run, summed by the whole block
     for (int k = 0; k < nheads; ++k) {
         const int th = L.heads[k];
         const int64_t ih = i0 + th, jh = ih + L.diag[th];
-        const double cbk = (KIND == ACAMP) ? T[jh] : 0.0;
+        const double cbk = (KIND == ACAMP) ? wsum_shift(T, jh) : 0.0;
         // two independent partial sums per thread (alternate strides), for
         // instruction-level parallelism in the serial double-double chains
-        DD q[FL_NQ], q2[FL_NQ];
-#pragma unroll
-        for (int r = 0; r < FL_NQ; ++r) q[r] = q2[r] = {0.0, 0.0};
+        DD q = {0.0, 0.0}, q2 = {0.0, 0.0};
         int l = t;
         for (; l + B < m; l += 2 * B) {
-            long_terms<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
-            long_terms<KIND, PC>(q2, T[ih + l + B], T[jh + l + B], ca, cbk, p, 1.0);
+            long_term<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
+            long_term<KIND, PC>(q2, T[ih + l + B], T[jh + l + B], ca, cbk, p, 1.0);
         }
-        if (l < m) long_terms<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
-#pragma unroll
-        for (int r = 0; r < FL_NQ; ++r) q[r] = dd_add(dd_norm(q[r]), dd_norm(q2[r]));
-#pragma unroll
-        for (int r = 0; r < NQ; ++r) {
-            const DD tot = dd_block_sum<B>(q[r], L.buf);
-            if (t == th) x[r] = tot;
-        }
+        if (l < m) long_term<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
+        const DD tot = dd_block_sum<B>(dd_add(dd_norm(q), dd_norm(q2)), L.buf);
+        if (t == th) x = tot;
         if (t == 0) L.cb[k] = cbk;
     }
     __syncthreads();
     // every other row of a run: its pair minus the preceding row's pair
+    const double cbr = (KIND == ACAMP && need) ? L.cb[run] : 0.0;
     if (need && !head) {
-        const double cbr = (KIND == ACAMP) ? L.cb[run] : 0.0;
-        long_terms<KIND, PC>(x, T[i + m - 1], T[j + m - 1], ca, cbr, p, 1.0);
-        long_terms<KIND, PC>(x, T[i - 1], T[j - 1], ca, cbr, p, -1.0);
-#pragma unroll
-        for (int r = 0; r < NQ; ++r) x[r] = dd_norm(x[r]);
+        long_term<KIND, PC>(x, T[i + m - 1], T[j + m - 1], ca, cbr, p, 1.0);
+        long_term<KIND, PC>(x, T[i - 1], T[j - 1], ca, cbr, p, -1.0);
+        x = dd_norm(x);
     }
-#pragma unroll
-    for (int r = 0; r < NQ; ++r) x[r] = dd_segment_scan<B>(head || !need, x[r], L.buf, L.ibuf);
+    x = dd_segment_scan<B>(head || !need, x, L.buf, L.ibuf);
     if (!need) return;
     double ex;
     if (KIND == ACAMP) {
+        // window sums from the statistics: the row's shifted by c_a (its
+        // block is this block), the column's moved to the run's c_b
+        const double *wa = s.wsum + 4 * i, *wb = s.wsum + 4 * j;
+        const DD sa = {wa[0], wa[1]}, qa = {wa[2], wa[3]};
+        const DD sj = {wb[0], wb[1]}, qj = {wb[2], wb[3]};
         const DD md = {(double)m, 0.0};
-        const DD mcov = dd_sub(dd_mul(md, x[0]), dd_mul(x[1], x[3]));
-        const DD ea = dd_sub(dd_mul(md, x[2]), dd_mul(x[1], x[1]));
-        const DD eb = dd_sub(dd_mul(md, x[4]), dd_mul(x[3], x[3]));
+        const DD sb = dd_add(sj, dd_mul(md, dd_two_sum(wsum_shift(T, j), -cbr)));
+        const DD mcov = dd_sub(dd_mul(md, x), dd_mul(sa, sb));
+        const DD ea = dd_sub(dd_mul(md, qa), dd_mul(sa, sa));
+        const DD eb = dd_sub(dd_mul(md, qj), dd_mul(sj, sj));
         const DD eab = dd_mul(ea, eb);
         const double prod = dd_val(eab);
         if (!(prod > 0.0)) {
@@ -363,7 +359,7 @@ __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallb
             ex = 2.0 * (double)m * omr;
         }
     } else {
-        ex = fmax(dd_val(x[0]), 0.0);
+        ex = fmax(dd_val(x), 0.0);
     }
     finalize_finish<KIND, PC>(s, fb, jb, i, j, ex, P, I);
 }

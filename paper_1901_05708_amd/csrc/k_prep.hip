@@ -32,7 +32,8 @@ constexpr int STATS_CHUNK = 64;    // steps per staged chunk
 // 2^-104 (Q / energy) relative error before its final rounding: far below
 // the two-pass sums' own m 2^-53 for any series whose windows vary above
 // 1e-10 of their offset from c. Constant windows are flagged exactly from
-// integer counts of sample changes, never from the energy.
+// integer counts of sample changes, never from the energy. S_j and Q_j are
+// kept (wsum) for the rescoring of z-normalized pairs.
 __device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, DD *dbuf,
                                                   int *ibuf)
 {
@@ -89,6 +90,12 @@ __device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, D
         s.mu[j] = mu;
         s.isconst[j] = same ? 1 : 0;
         s.invn[j] = (same || !(ss > 0.0)) ? 0.0 : 1.0 / sqrt(ss);
+        // the exact sums, for the rescoring of long windows
+        double *ws = s.wsum + 4 * j;
+        ws[0] = Sj.hi;
+        ws[1] = Sj.lo;
+        ws[2] = Qj.hi;
+        ws[3] = Qj.lo;
     }
 }
 

@@ -63,6 +63,10 @@ struct Series {
     double *mu;
     double *invn;
     uint8_t *isconst;
+    // ACAMP with m >= LONG_WINDOW: 4 N entries, for window j the double-double
+    // sums S = sum u, Q = sum u^2 (hi, lo, hi, lo) of its samples shifted by
+    // c = t[256 floor(j / 256)], u = t - c (k_window_stats).
+    double *wsum;
     // Packed (value, index) keys, N entries; ~0 = no candidate.
     unsigned long long *keys;
     // FP32 copies of the streams (MP_FP32_REFRESH), recentred before rounding:
