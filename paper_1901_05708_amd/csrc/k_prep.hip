@@ -49,13 +49,13 @@ __device__ __forceinline__ void window_stats_long(const Series &s, int64_t j0, D
     for (int l = t; l < m; l += STATS_BLOCK) {
         const double v = T[j0 + l];
         const DD u = dd_two_sum(v, -c);
-        S = dd_add(S, u);
-        Q = dd_add(Q, dd_mul(u, u));
+        dd_acc(S, u);
+        dd_acc(Q, dd_mul(u, u));
         if (l > 0) brk += (v != T[j0 + l - 1]) ? 1 : 0;
     }
     // block totals (the last thread of each inclusive scan holds them)
-    const DD S0 = dd_block_sum<STATS_BLOCK>(S, dbuf);
-    const DD Q0 = dd_block_sum<STATS_BLOCK>(Q, dbuf);
+    const DD S0 = dd_block_sum<STATS_BLOCK>(dd_norm(S), dbuf);
+    const DD Q0 = dd_block_sum<STATS_BLOCK>(dd_norm(Q), dbuf);
     brk = int_block_scan<STATS_BLOCK>(brk, ibuf);
     const int B0 = ibuf[STATS_BLOCK - 1];
     __syncthreads();

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import check_profile
+from tests.parity import atol_for, check_profile
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +94,30 @@ def test_noalloc_matches_existing_entry_point(mp, kind, p, m, precision, R, n1, 
             atol = 1e-6 if kind == "acamp" else 0.0
             check_profile(T, m, kind, p, excl, Pn, In, Pr, Ir, Qr, rtol, atol,
                           label=f"noalloc-{kind}-{precision}")
+
+
+def test_noalloc_long_windows(mp):
+    """m = 2048 (z-normalized): the window statistics keep each window's
+    sums in the static array and the rescoring reads them back; bit for bit
+    against the allocating call on two calls in a row, the second smaller,
+    and against the oracle on sampled rows."""
+    import torch
+    m, excl = 2048, W.excl_default(2048)
+    rng = np.random.default_rng(2048)
+    for call, n in enumerate((14000, 9000)):
+        T = np.cumsum(rng.standard_normal(n))
+        T[n // 2:n // 2 + 600] = T[n // 2]
+        Td = torch.as_tensor(T, dtype=torch.float64, device="cuda")
+        _note(f"noalloc long windows call {call} n={n} m={m}")
+        Pn, In = _noalloc_abi(mp, "acamp", Td, m, 2.0, excl, "fp64", 8192)
+        Pe, Ie = _existing(mp, "acamp", Td, m, 2.0, excl, "fp64", 8192)
+        torch.cuda.synchronize()
+        assert torch.equal(In, Ie) and torch.equal(Pn, Pe), f"call {call}"
+    rows = np.unique(np.concatenate([W.sample_rows(n - m + 1, 64, 9),
+                                     np.arange(n // 2 - m - 2, n // 2 - m + 3)]))
+    Pr, Ir, Qr = oracle.profile(T, m, "acamp", rows=rows, excl=excl)
+    check_profile(T, m, "acamp", 2.0, excl, Pn.cpu().numpy()[rows], In.cpu().numpy()[rows],
+                  Pr, Ir, Qr, 1e-9, atol_for("acamp", m), rows=rows, label="noalloc-long")
 
 
 def test_noalloc_at_the_window_limit(mp):
