@@ -69,6 +69,8 @@ struct Workspace {
     float *xf = nullptr, *yf = nullptr, *zf = nullptr;
     double *mu = nullptr, *invn = nullptr;
     double *wsum = nullptr;            // 4 x key_cap: window sums of long z-normalized windows
+    int32_t *lcount = nullptr, *lhead = nullptr;   // long-window rescoring: runs per block
+    double *lanchor = nullptr;         // 2 x key_cap: and their exact first sums
     uint8_t *isconst = nullptr;
     unsigned long long *keys = nullptr;
     // exact-search queue (key_cap entries) and pivot distances
@@ -122,9 +124,11 @@ void free_arrays(Workspace &w)
 {
     void *ptrs[] = {w.x,       w.y,      w.z,       w.xf,    w.yf,    w.zf,
                     w.mu,      w.invn,   w.wsum,    w.isconst, w.keys, w.fb_rows,
-                    w.fb_job,  w.fb_keys, w.fb_ub,  w.fb_pd, w.counters};
+                    w.fb_job,  w.fb_keys, w.fb_ub,  w.fb_pd, w.counters, w.lcount,
+                    w.lhead,   w.lanchor};
     for (void *p : ptrs) hipFree(p);
-    w.x = w.y = w.z = w.mu = w.invn = w.wsum = w.fb_ub = nullptr;
+    w.x = w.y = w.z = w.mu = w.invn = w.wsum = w.fb_ub = w.lanchor = nullptr;
+    w.lcount = w.lhead = nullptr;
     w.xf = w.yf = w.zf = w.fb_pd = nullptr;
     w.isconst = nullptr;
     w.keys = w.fb_keys = nullptr;
@@ -229,6 +233,9 @@ int ensure_arrays(Workspace &w, int64_t streams, int64_t keys)
         (rc = grow(&w.yf, scap, "workspace yf")) || (rc = grow(&w.zf, scap, "workspace zf")) ||
         (rc = grow(&w.mu, kcap, "workspace mu")) || (rc = grow(&w.invn, kcap, "workspace invn")) ||
         (rc = grow(&w.wsum, (size_t)kcap * 4, "workspace window sums")) ||
+        (rc = grow(&w.lcount, kcap, "workspace rescoring runs")) ||
+        (rc = grow(&w.lhead, kcap, "workspace rescoring runs")) ||
+        (rc = grow(&w.lanchor, (size_t)kcap * 2, "workspace rescoring anchors")) ||
         (rc = grow(&w.isconst, kcap, "workspace const")) ||
         (rc = grow(&w.keys, kcap, "workspace keys")) ||
         (rc = grow(&w.fb_rows, kcap, "workspace fallback rows")) ||
@@ -709,6 +716,9 @@ void bind(Layout &L, const Workspace &w)
         s.mu = w.mu + ko;
         s.invn = w.invn + ko;
         s.wsum = w.wsum + 4 * ko;
+        s.lcount = w.lcount + ko;
+        s.lhead = w.lhead + ko;
+        s.lanchor = w.lanchor + 2 * ko;
         s.isconst = w.isconst + ko;
         s.keys = w.keys + ko;
     }
@@ -748,6 +758,7 @@ Batch make_batch(const Layout &L, const Workspace &w, const Tables &t)
     fb.pd_stride = w.key_cap;
     fb.capacity = (int32_t)std::min<int64_t>(L.key_total, INT32_MAX);
     b.visits = L.count ? w.visits : nullptr;
+    for (const Job &j : L.jobs) b.long_jobs |= j.s.m >= LONG_WINDOW ? 1 : 0;
     return b;
 }
 
@@ -1290,7 +1301,7 @@ int run_batch(const double *T_cat, const mp_job *jobs, int32_t njobs, int32_t pr
 // STREAM_PAD per series), the window statistics, the key, the exact-search
 // queue entry and FB_PIVOTS pivot distances: 149 bytes, 39.2 MB at the limit.
 constexpr int64_t NOALLOC_MAX_N = MP_NOALLOC_MAX_N;
-constexpr size_t NOALLOC_BYTES = (size_t)48 << 20;
+constexpr size_t NOALLOC_BYTES = (size_t)56 << 20;
 constexpr size_t NOALLOC_ALIGN = 256;
 
 // Sub-allocator over the array: slices of at least NOALLOC_ALIGN bytes, in
@@ -1322,6 +1333,9 @@ void carve(Carver &c, const Layout &L, Workspace *w, Tables *t)
     w->mu = c.take<double>(K);
     w->invn = c.take<double>(K);
     w->wsum = c.take<double>(4 * K);
+    w->lcount = c.take<int32_t>(K);
+    w->lhead = c.take<int32_t>(K);
+    w->lanchor = c.take<double>(2 * K);
     w->isconst = c.take<uint8_t>(K);
     w->keys = c.take<unsigned long long>(K);
     w->fb_rows = c.take<int32_t>(K);
@@ -1348,9 +1362,9 @@ constexpr size_t noalloc_bytes_at_limit()
     constexpr size_t A = NOALLOC_ALIGN;
     constexpr size_t S = (size_t)(NOALLOC_MAX_N + STREAM_PAD), K = (size_t)NOALLOC_MAX_N;
     constexpr size_t per_array = A;   // rounding slack of each slice
-    return 3 * (8 * S) + 3 * (4 * S) + K * (8 + 8 + 32 + 1 + 8 + 4 + 4 + 8 + 8 + 4 * FB_PIVOTS) +
-           64 * 4 + 8 + sizeof(Job) + 4 * 8 + (K / 512 + 2) * 8 + 4 + FB_PIVOTS * 4 +
-           26 * per_array;
+    return 3 * (8 * S) + 3 * (4 * S) +
+           K * (8 + 8 + 32 + 4 + 4 + 16 + 1 + 8 + 4 + 4 + 8 + 8 + 4 * FB_PIVOTS) + 64 * 4 + 8 +
+           sizeof(Job) + 4 * 8 + (K / 512 + 2) * 8 + 4 + FB_PIVOTS * 4 + 29 * per_array;
 }
 static_assert(noalloc_bytes_at_limit() <= NOALLOC_BYTES,
               "the static array holds a series of MP_NOALLOC_MAX_N windows");

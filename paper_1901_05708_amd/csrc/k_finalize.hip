@@ -207,8 +207,9 @@ __device__ __forceinline__ void finalize_block(const Series &s, const Fallback &
 // then the sum of row i follows from that of row i - 1 by adding the term of
 // the pair that enters (i + m - 1, j + m - 1) and subtracting the one that
 // leaves (i - 1, j - 1). A block of 256 rows splits into runs of consecutive
-// rows with a common winner diagonal; the whole block sums each run's first
-// pair over its m terms, and a segmented prefix sum carries it along the run.
+// rows with a common winner diagonal; each run's first pair is summed over
+// its m terms by a block of its own, and a segmented prefix sum carries it
+// along the run.
 // All of it is double-double (dd.h), so the running sums lose about 2^-104 of
 // their largest partial sum to cancellation instead of 2^-53. The quantities:
 //   AAMP, p-norm: the sum of (a - b)^2 or |a - b|^p (the terms rounded as in
@@ -265,66 +266,126 @@ __device__ __forceinline__ double wsum_shift(const gptr<double> T, int64_t j)
     return T[j & ~(int64_t)(FIN_BLOCK - 1)];
 }
 
-// A block whose rows split into more runs than this sums every row directly
-// (the anchors are serial within a block). Thresholds of 1-96 timed within
-// noise of 48 for the Euclidean distance; for z-normalized pairs 48 timed
-// best of 16, 32 and 48 at m = 16384 and 65536 (runs of at most 48 cover
-// nearly every block of the uniform series there).
-constexpr int LONG_RUNS_MAX = 48;
+// Blocks of step 2 per block of rows: block g sums the anchors of runs
+// g, g + LONG_ANCHOR_SPLIT, ... of its block of rows (most blocks of rows
+// hold a few runs; every run of a block of 256 rows can be a single row).
+constexpr int LONG_ANCHOR_SPLIT = 16;
 
+// finalize_decode without its side effects (the later steps of the
+// long-window rescoring read the keys again): whether row i has a winner to
+// rescore, and which.
+template <int KIND>
+__device__ __forceinline__ bool decode_quiet(const Series &s, int64_t i, int64_t *j_out)
+{
+    const unsigned long long mask = (1ull << s.gb) - 1ull;
+    const unsigned long long key = s.keys[i];
+    if ((KIND == ACAMP && s.isconst[i]) || key == KEY_NONE) return false;
+    const int64_t j = (int64_t)(key & mask);
+    if (!legal_pair(s, i, j)) return false;
+    *j_out = j;
+    return true;
+}
+
+// Runs of a block: consecutive rows that need a sum and share the winner
+// diagonal dg. Returns their number; head / run tell whether this thread's
+// row starts a run and the index of its run. Every thread of the block calls it.
+__device__ __forceinline__ int long_runs(bool need, long long dg, FinLongLds &L, bool &head,
+                                         int &run)
+{
+    const int t = threadIdx.x;
+    const long long d = need ? dg : LLONG_MIN;
+    L.diag[t] = d;
+    __syncthreads();
+    head = need && (t == 0 || L.diag[t - 1] != d);
+    run = int_block_scan<FIN_BLOCK>(head ? 1 : 0, L.ibuf) - 1;
+    const int nh = L.ibuf[FIN_BLOCK - 1];
+    __syncthreads();
+    return nh;
+}
+
+// Rescoring of long windows, in three launches, so that the runs' exact first
+// sums (the anchors) are spread over the GPU instead of being taken one after
+// another by the block of their rows:
+//  1. (k_finalize) decode the block's winners, find its runs and record them
+//     (lcount, lhead);
+//  2. (k_long_anchors) a block per run sums the run's first pair;
+//  3. (k_long_finish) each block slides the anchors along its runs and
+//     finishes its rows.
 template <int KIND, int PC>
 __device__ __forceinline__ void finalize_block_long(const Series &s, const Fallback &fb,
                                                     int32_t jb, int64_t i0, double *P,
                                                     int64_t *I, unsigned char *lds)
 {
     FinLongLds &L = *reinterpret_cast<FinLongLds *>(lds);
-    constexpr int B = FIN_BLOCK;
     const int t = threadIdx.x;
     const int64_t i = i0 + t;
     int64_t j = 0;
     const bool need = i < s.N && finalize_decode<KIND>(s, fb, jb, i, P, I, &j);
-    const long long dg = need ? (long long)(j - i) : LLONG_MIN;
-    L.diag[t] = dg;
-    __syncthreads();
-    // runs: consecutive rows that need a sum and share the winner diagonal
-    const bool head = need && (t == 0 || L.diag[t - 1] != dg);
-    const int run = int_block_scan<B>(head ? 1 : 0, L.ibuf) - 1;
-    const int nheads = L.ibuf[B - 1];
-    __syncthreads();
-    if (nheads > LONG_RUNS_MAX) {   // block-uniform
-        finalize_block_sums<KIND, PC>(s, fb, jb, i0, need, j, P, I,
-                                      *reinterpret_cast<FinLds *>(lds));
-        return;
-    }
-    if (head) L.heads[run] = t;
-    __syncthreads();
+    bool head;
+    int run;
+    const int nheads = long_runs(need, (long long)(j - i), L, head, run);
+    if (head) s.lhead[i0 + run] = t;
+    if (t == 0) s.lcount[i0] = nheads;
+}
+
+// Step 2: the exact sum of the first pair of run k of the block of rows from
+// i0, by the whole block (two independent partial sums per thread, for
+// instruction-level parallelism in the serial double-double chains).
+template <int KIND, int PC>
+__device__ __forceinline__ void long_anchor(const Series &s, int64_t i0, int k, DD *buf)
+{
+    constexpr int B = FIN_BLOCK;
+    const int t = threadIdx.x;
+    const int64_t ih = i0 + s.lhead[i0 + k];
+    int64_t jh = 0;
+    decode_quiet<KIND>(s, ih, &jh);   // a run's first row has a winner
     const gptr<double> T = as_global(s.T);
     const int m = s.m;
     const double p = s.p;
     const double ca = (KIND == ACAMP) ? T[i0] : 0.0;
-    DD x = {0.0, 0.0};
-    // the first pair of every run, summed by the whole block
-    for (int k = 0; k < nheads; ++k) {
-        const int th = L.heads[k];
-        const int64_t ih = i0 + th, jh = ih + L.diag[th];
-        const double cbk = (KIND == ACAMP) ? wsum_shift(T, jh) : 0.0;
-        // two independent partial sums per thread (alternate strides), for
-        // instruction-level parallelism in the serial double-double chains
-        DD q = {0.0, 0.0}, q2 = {0.0, 0.0};
-        int l = t;
-        for (; l + B < m; l += 2 * B) {
-            long_term<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
-            long_term<KIND, PC>(q2, T[ih + l + B], T[jh + l + B], ca, cbk, p, 1.0);
-        }
-        if (l < m) long_term<KIND, PC>(q, T[ih + l], T[jh + l], ca, cbk, p, 1.0);
-        const DD tot = dd_block_sum<B>(dd_add(dd_norm(q), dd_norm(q2)), L.buf);
-        if (t == th) x = tot;
-        if (t == 0) L.cb[k] = cbk;
+    const double cb = (KIND == ACAMP) ? wsum_shift(T, jh) : 0.0;
+    DD q = {0.0, 0.0}, q2 = {0.0, 0.0};
+    int l = t;
+    for (; l + B < m; l += 2 * B) {
+        long_term<KIND, PC>(q, T[ih + l], T[jh + l], ca, cb, p, 1.0);
+        long_term<KIND, PC>(q2, T[ih + l + B], T[jh + l + B], ca, cb, p, 1.0);
     }
+    if (l < m) long_term<KIND, PC>(q, T[ih + l], T[jh + l], ca, cb, p, 1.0);
+    const DD tot = dd_block_sum<B>(dd_add(dd_norm(q), dd_norm(q2)), buf);
+    if (t == 0) {
+        s.lanchor[2 * (i0 + k)] = tot.hi;
+        s.lanchor[2 * (i0 + k) + 1] = tot.lo;
+    }
+}
+
+// Step 3: every other row of a run is its preceding row's sum plus the pair
+// entering minus the pair leaving; a segmented prefix sum carries the
+// anchors along the runs.
+template <int KIND, int PC>
+__device__ __forceinline__ void finalize_block_long_finish(const Series &s, const Fallback &fb,
+                                                           int32_t jb, int64_t i0, double *P,
+                                                           int64_t *I, unsigned char *lds)
+{
+    FinLongLds &L = *reinterpret_cast<FinLongLds *>(lds);
+    constexpr int B = FIN_BLOCK;
+    const int t = threadIdx.x;
+    const int64_t i = i0 + t;
+    int64_t j = 0;
+    const bool need = i < s.N && decode_quiet<KIND>(s, i, &j);
+    bool head;
+    int run;
+    long_runs(need, (long long)(j - i), L, head, run);
+    const gptr<double> T = as_global(s.T);
+    const int m = s.m;
+    const double p = s.p;
+    const double ca = (KIND == ACAMP) ? T[i0] : 0.0;
+    if (KIND == ACAMP && head) L.cb[run] = wsum_shift(T, j);
     __syncthreads();
-    // every other row of a run: its pair minus the preceding row's pair
     const double cbr = (KIND == ACAMP && need) ? L.cb[run] : 0.0;
-    if (need && !head) {
+    DD x = {0.0, 0.0};
+    if (head) {
+        x = {s.lanchor[2 * (i0 + run)], s.lanchor[2 * (i0 + run) + 1]};
+    } else if (need) {
         long_term<KIND, PC>(x, T[i + m - 1], T[j + m - 1], ca, cbr, p, 1.0);
         long_term<KIND, PC>(x, T[i - 1], T[j - 1], ca, cbr, p, -1.0);
         x = dd_norm(x);
@@ -391,6 +452,52 @@ __global__ void __launch_bounds__(FIN_BLOCK) k_finalize(Batch b)
     case SEL_P1: finalize_block<PNORM, P_ONE>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
     case SEL_P3: finalize_block<PNORM, P_THREE>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
     default: finalize_block<PNORM, P_GENERIC>(J.s, b.fb, jb, i0, J.P, J.I, L); break;
+    }
+}
+
+// Step 2 of the long-window rescoring. Grid: x over (g, block of rows), g
+// major (the blocks of first runs come first), y over jobs.
+__global__ void __launch_bounds__(FIN_BLOCK) k_long_anchors(Batch b, int32_t nblk)
+{
+    const int32_t jb = blockIdx.y;
+    const Job J = load_uniform(&b.jobs[jb]);
+    if (J.s.m < LONG_WINDOW) return;
+    const int g = (int)(blockIdx.x / (uint32_t)nblk);
+    const int64_t i0 = (int64_t)(blockIdx.x - (uint32_t)g * (uint32_t)nblk) * FIN_BLOCK;
+    if (i0 >= J.s.N) return;   // block-uniform
+    const int nheads = J.s.lcount[i0];
+    __shared__ DD buf[FIN_BLOCK];
+    for (int k = g; k < nheads; k += LONG_ANCHOR_SPLIT) {
+        switch (sel_of(J.s.kind, J.s.pclass)) {
+        case SEL_AAMP: long_anchor<AAMP, P_TWO>(J.s, i0, k, buf); break;
+        case SEL_ACAMP: long_anchor<ACAMP, P_TWO>(J.s, i0, k, buf); break;
+        case SEL_P1: long_anchor<PNORM, P_ONE>(J.s, i0, k, buf); break;
+        case SEL_P3: long_anchor<PNORM, P_THREE>(J.s, i0, k, buf); break;
+        default: long_anchor<PNORM, P_GENERIC>(J.s, i0, k, buf); break;
+        }
+    }
+}
+
+// Step 3 of the long-window rescoring. Grid as k_finalize's.
+__global__ void __launch_bounds__(FIN_BLOCK) k_long_finish(Batch b)
+{
+    const int32_t jb = blockIdx.y;
+    const Job J = load_uniform(&b.jobs[jb]);
+    const int64_t i0 = (int64_t)blockIdx.x * FIN_BLOCK;
+    if (J.s.m < LONG_WINDOW || i0 >= J.s.N) return;   // block-uniform
+    __shared__ __align__(16) unsigned char lds[sizeof(FinLongLds)];
+    switch (sel_of(J.s.kind, J.s.pclass)) {
+    case SEL_AAMP: finalize_block_long_finish<AAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, lds); break;
+    case SEL_ACAMP:
+        finalize_block_long_finish<ACAMP, P_TWO>(J.s, b.fb, jb, i0, J.P, J.I, lds);
+        break;
+    case SEL_P1: finalize_block_long_finish<PNORM, P_ONE>(J.s, b.fb, jb, i0, J.P, J.I, lds); break;
+    case SEL_P3:
+        finalize_block_long_finish<PNORM, P_THREE>(J.s, b.fb, jb, i0, J.P, J.I, lds);
+        break;
+    default:
+        finalize_block_long_finish<PNORM, P_GENERIC>(J.s, b.fb, jb, i0, J.P, J.I, lds);
+        break;
     }
 }
 
@@ -696,8 +803,15 @@ hipError_t launch_any_merge(const double *Pn, const int64_t *In, double *P, int6
 hipError_t launch_finalize(const Batch &b, hipStream_t st)
 {
     if (b.njobs <= 0) return hipSuccess;
-    dim3 g((unsigned)((b.max_N + FIN_BLOCK - 1) / FIN_BLOCK), (unsigned)b.njobs);
+    const int64_t nblk = (b.max_N + FIN_BLOCK - 1) / FIN_BLOCK;
+    dim3 g((unsigned)nblk, (unsigned)b.njobs);
     hipLaunchKernelGGL(k_finalize, g, dim3(FIN_BLOCK), 0, st, b);
+    if (b.long_jobs) {
+        if (nblk * LONG_ANCHOR_SPLIT > INT32_MAX) return hipErrorInvalidValue;
+        dim3 ga((unsigned)(nblk * LONG_ANCHOR_SPLIT), (unsigned)b.njobs);
+        hipLaunchKernelGGL(k_long_anchors, ga, dim3(FIN_BLOCK), 0, st, b, (int32_t)nblk);
+        hipLaunchKernelGGL(k_long_finish, g, dim3(FIN_BLOCK), 0, st, b);
+    }
     return hipGetLastError();
 }
 

@@ -67,6 +67,13 @@ struct Series {
     // sums S = sum u, Q = sum u^2 (hi, lo, hi, lo) of its samples shifted by
     // c = t[256 floor(j / 256)], u = t - c (k_window_stats).
     double *wsum;
+    // Rescoring of long windows (m >= LONG_WINDOW), per block of 256 rows
+    // from i0: lcount[i0] its number of runs,
+    // lhead[i0 + k] the row offset of run k's first row, lanchor[2 (i0 + k)]
+    // that row's exact sum (double-double); N entries each (2 N for lanchor).
+    int32_t *lcount;
+    int32_t *lhead;
+    double *lanchor;
     // Packed (value, index) keys, N entries; ~0 = no candidate.
     unsigned long long *keys;
     // FP32 copies of the streams (MP_FP32_REFRESH), recentred before rounding:
@@ -185,6 +192,8 @@ struct Batch {
     int64_t simple_segs;       // largest segment count of the simple kernel's jobs
     Fallback fb;
     unsigned long long *visits;    // pair-visit counter (test mode), else null
+    int32_t long_jobs;             // 1: some job has m >= LONG_WINDOW (rescored in three steps)
+    int32_t pad2;
 };
 
 // Kernel selectors: which distance specialisations a launch contains.
