@@ -517,6 +517,7 @@ struct Group {
     int32_t grid = 0;
     int32_t kd = 8;            // diagonals per lane
     bool fp32 = false;
+    int32_t wpb = 1;           // waves per block of the sweep launch
 };
 
 // A launch laid out: the job table (pointers bound to a workspace by bind())
@@ -695,6 +696,14 @@ int make_layout(const std::vector<Spec> &specs, int32_t precision, const Tuning 
         // at least 64 rows per wave
         g.grid = (int32_t)std::max<int64_t>(
             1, std::min<int64_t>(slots * std::max(1, tu.grid_mult), g.rows / 64));
+        // A grid capped below the kernel's occupancy runs in blocks of four
+        // waves: blocks of one wave have landed two on one SIMD and none on
+        // another (up to 1.4 times the sweep time), a block's four waves go
+        // to four SIMDs.
+        if (wps > 0 && !L.count && g.grid >= 4 && band_has_wave_blocks(g.sels, g.kd, g.fp32)) {
+            g.wpb = 4;
+            g.grid -= g.grid % 4;
+        }
         L.items += g.grid;
     }
     *out = std::move(L);
@@ -784,7 +793,7 @@ int enqueue(const Batch &b, const Layout &L, hipStream_t st, EvSet *es)
     if (es) HIP_TRY(hipEventRecord(es->ev[1], st), "hipEventRecord");
     for (const Group &g : L.groups)
         if (g.grid)
-            HIP_TRY(launch_sweep_band(group_view(b, g), g.sels, g.kd, g.fp32, g.grid, st),
+            HIP_TRY(launch_sweep_band(group_view(b, g), g.sels, g.kd, g.fp32, g.grid, g.wpb, st),
                     "sweep launch");
     if (L.simple_diag > 0) HIP_TRY(launch_sweep_simple(b, st), "sweep launch");
     if (es) HIP_TRY(hipEventRecord(es->ev[2], st), "hipEventRecord");

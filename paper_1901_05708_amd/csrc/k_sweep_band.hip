@@ -257,7 +257,7 @@ __device__ __forceinline__ F acamp_key(F S, F ri, F cj)
 // back as broadcasts; otherwise it takes them as scalar loads (the kernels
 // that run 3 waves per SIMD on 168 registers, where holding them in vector
 // registers spills in the recurrence loop).
-template <int KIND, int PC, int KD, typename F, bool COUNT, bool ROWS_LDS>
+template <int KIND, int PC, int KD, typename F, bool COUNT, bool ROWS_LDS, int WPB>
 __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, const int64_t i0,
                                           const int64_t i1, F *ring, F *rowbuf, F *rowop,
                                           double *stage, unsigned long long *visits)
@@ -266,7 +266,9 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
     constexpr int WD = 64 * KD;          // diagonals per item
     constexpr int RING = WD;             // ring entries per field
 
-    const int lane = threadIdx.x;
+    // (blocks of one wave use threadIdx.x as it is: masking it changes the
+    // schedule of the ring writes)
+    const int lane = WPB == 1 ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     const int64_t N = s.N;
     const uint32_t notmask = ~(uint32_t)(WD - 1);
     const unsigned long long gmask = (1ull << s.gb) - 1ull;
@@ -711,9 +713,13 @@ constexpr int waves_target()
 
 // The persistent sweep over every band of every job of a launch. SELS is the
 // set of distance specialisations the launch holds: a single one gets a kernel
-// of its own; a mix dispatches per item (the branch is wave-uniform).
-template <uint32_t SELS, int KD, typename F, bool COUNT>
-__global__ void __launch_bounds__(64)
+// of its own; a mix dispatches per item (the branch is wave-uniform). Each
+// wave is a persistent worker of its own; a block holds WPB of them (4 for
+// grids capped at one or two waves per SIMD: the hardware places a block's
+// four waves on four SIMDs, while blocks of one wave can land two on a SIMD
+// and none on another).
+template <uint32_t SELS, int KD, typename F, bool COUNT, int WPB>
+__global__ void __launch_bounds__(64 * WPB)
     __attribute__((amdgpu_waves_per_eu(waves_target<SELS, KD, F>()))) k_sweep_band(Batch b)
 {
     constexpr int RING = 64 * KD;
@@ -721,7 +727,9 @@ __global__ void __launch_bounds__(64)
     // ring fields, row transpose, recentred row operands (FP32 only)
     constexpr int SWEEP_D = (int)(((NF * RING + NRB * 64 + 2 * KD) * sizeof(F) + 7) / 8);
     constexpr int LDS_D = SWEEP_D > stage_doubles<KD>() ? SWEEP_D : stage_doubles<KD>();
-    __shared__ double lds[LDS_D];
+    __shared__ double lds_all[WPB * LDS_D];
+    const int wv = WPB == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    double *lds = lds_all + wv * LDS_D;   // this wave's part
     F *ring = reinterpret_cast<F *>(lds);
     F *rowbuf = ring + NF * RING;
     F *rowop = rowbuf + NRB * 64;
@@ -737,8 +745,8 @@ __global__ void __launch_bounds__(64)
     // by band_cost positions that stand for its exact restart, so equal
     // position ranges are nearly equal work. share = total / G positions, the
     // first total % G waves take one more.
-    const int64_t G = gridDim.x;
-    const int64_t w = blockIdx.x;
+    const int64_t G = (int64_t)gridDim.x * WPB;
+    const int64_t w = (int64_t)blockIdx.x * WPB + wv;
     const int64_t qrows = total / G, rrows = total % G;
     int64_t pos = uniform64(w * qrows + min(w, rrows));
     const int64_t pend = uniform64(pos + qrows + (w < rrows ? 1 : 0));
@@ -782,16 +790,16 @@ __global__ void __launch_bounds__(64)
         pos = row0 + i1;
         const uint32_t sel = sel_of(s.kind, s.pclass);
         if ((SELS & SEL_AAMP) && sel == SEL_AAMP)
-            band_item<AAMP, P_TWO, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<AAMP, P_TWO, KD, F, COUNT, RL, WPB>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_ACAMP) && sel == SEL_ACAMP)
-            band_item<ACAMP, (SELS & SEL_FCMP) ? P_FCMP : P_TWO, KD, F, COUNT, RL>(
+            band_item<ACAMP, (SELS & SEL_FCMP) ? P_FCMP : P_TWO, KD, F, COUNT, RL, WPB>(
                 s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_P1) && sel == SEL_P1)
-            band_item<PNORM, P_ONE, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<PNORM, P_ONE, KD, F, COUNT, RL, WPB>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_P3) && sel == SEL_P3)
-            band_item<PNORM, P_THREE, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<PNORM, P_THREE, KD, F, COUNT, RL, WPB>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
         else if ((SELS & SEL_PGEN) && sel == SEL_PGEN)
-            band_item<PNORM, P_GENERIC, KD, F, COUNT, RL>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
+            band_item<PNORM, P_GENERIC, KD, F, COUNT, RL, WPB>(s, k_lo, i0, i1, ring, rowbuf, rowop, stage, b.visits);
     }
 }
 
@@ -860,30 +868,55 @@ const void *band_kernel(uint32_t sels, bool count)
 {
     if constexpr (sizeof(F) == 8) {
         if (sels == SEL_PGEN)
-            return count ? (const void *)k_sweep_band<SEL_PGEN, KD, F, true>
-                         : (const void *)k_sweep_band<SEL_PGEN, KD, F, false>;
+            return count ? (const void *)k_sweep_band<SEL_PGEN, KD, F, true, 1>
+                         : (const void *)k_sweep_band<SEL_PGEN, KD, F, false, 1>;
         // ACAMP keyed on F: launches of such jobs alone (pair counting runs
         // the mixed kernel, which visits the same pairs)
         if (sels == (SEL_ACAMP | SEL_FCMP) && !count)
-            return (const void *)k_sweep_band<SEL_ACAMP | SEL_FCMP, KD, F, false>;
+            return (const void *)k_sweep_band<SEL_ACAMP | SEL_FCMP, KD, F, false, 1>;
         // long windows of the Euclidean and p = 1, 3 distances
         if ((sels & SEL_LONG) && !count) {
             switch (sels & SEL_BAND) {
-            case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP | SEL_LONG, KD, F, false>;
-            case SEL_P1: return (const void *)k_sweep_band<SEL_P1 | SEL_LONG, KD, F, false>;
-            case SEL_P3: return (const void *)k_sweep_band<SEL_P3 | SEL_LONG, KD, F, false>;
+            case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP | SEL_LONG, KD, F, false, 1>;
+            case SEL_P1: return (const void *)k_sweep_band<SEL_P1 | SEL_LONG, KD, F, false, 1>;
+            case SEL_P3: return (const void *)k_sweep_band<SEL_P3 | SEL_LONG, KD, F, false, 1>;
             default: break;
             }
         }
     }
-    if (count) return (const void *)k_sweep_band<SEL_BAND, KD, F, true>;
+    if (count) return (const void *)k_sweep_band<SEL_BAND, KD, F, true, 1>;
     switch (sels & SEL_BAND) {
-    case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP, KD, F, false>;
-    case SEL_ACAMP: return (const void *)k_sweep_band<SEL_ACAMP, KD, F, false>;
-    case SEL_P1: return (const void *)k_sweep_band<SEL_P1, KD, F, false>;
-    case SEL_P3: return (const void *)k_sweep_band<SEL_P3, KD, F, false>;
-    default: return (const void *)k_sweep_band<SEL_BAND, KD, F, false>;
+    case SEL_AAMP: return (const void *)k_sweep_band<SEL_AAMP, KD, F, false, 1>;
+    case SEL_ACAMP: return (const void *)k_sweep_band<SEL_ACAMP, KD, F, false, 1>;
+    case SEL_P1: return (const void *)k_sweep_band<SEL_P1, KD, F, false, 1>;
+    case SEL_P3: return (const void *)k_sweep_band<SEL_P3, KD, F, false, 1>;
+    default: return (const void *)k_sweep_band<SEL_BAND, KD, F, false, 1>;
     }
+}
+
+// Blocks of four waves, for the selector sets that run on capped grids (long
+// windows); null where there is none.
+template <int KD, typename F>
+const void *band_kernel4(uint32_t sels)
+{
+    if constexpr (KD == 8 && sizeof(F) == 8) {
+        switch (sels) {
+        case SEL_AAMP | SEL_LONG: return (const void *)k_sweep_band<SEL_AAMP | SEL_LONG, KD, F, false, 4>;
+        case SEL_P1 | SEL_LONG: return (const void *)k_sweep_band<SEL_P1 | SEL_LONG, KD, F, false, 4>;
+        case SEL_P3 | SEL_LONG: return (const void *)k_sweep_band<SEL_P3 | SEL_LONG, KD, F, false, 4>;
+        case SEL_ACAMP: return (const void *)k_sweep_band<SEL_ACAMP, KD, F, false, 4>;
+        case SEL_ACAMP | SEL_FCMP:
+            return (const void *)k_sweep_band<SEL_ACAMP | SEL_FCMP, KD, F, false, 4>;
+        default: return nullptr;
+        }
+    } else if constexpr (KD == 8) {
+        switch (sels) {
+        case SEL_ACAMP: return (const void *)k_sweep_band<SEL_ACAMP, KD, F, false, 4>;
+        case SEL_P1: return (const void *)k_sweep_band<SEL_P1, KD, F, false, 4>;
+        default: return nullptr;
+        }
+    }
+    return nullptr;
 }
 
 const void *band_kernel_for(uint32_t sels, int32_t kd, bool fp32, bool count)
@@ -895,14 +928,28 @@ const void *band_kernel_for(uint32_t sels, int32_t kd, bool fp32, bool count)
 
 }  // namespace
 
+bool band_has_wave_blocks(uint32_t sels, int32_t diags_per_lane, bool fp32)
+{
+    if (diags_per_lane != 8) return false;
+    return (fp32 ? band_kernel4<8, float>(sels) : band_kernel4<8, double>(sels)) != nullptr;
+}
+
 hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_lane, bool fp32,
-                             int32_t grid, hipStream_t st)
+                             int32_t grid, int32_t wpb, hipStream_t st)
 {
     if (grid <= 0 || !(sels & (SEL_BAND | SEL_PGEN))) return hipSuccess;
     const void *k = band_kernel_for(sels, diags_per_lane, fp32, b.visits != nullptr);
+    if (wpb == 4) {
+        k = (diags_per_lane == 8 && b.visits == nullptr)
+                ? (fp32 ? band_kernel4<8, float>(sels) : band_kernel4<8, double>(sels))
+                : nullptr;
+        if (!k || grid % 4) return hipErrorInvalidValue;
+    } else if (wpb != 1) {
+        return hipErrorInvalidValue;
+    }
     Batch arg = b;
     void *args[] = {&arg};
-    return hipLaunchKernel(k, dim3(grid), dim3(64), args, 0, st);
+    return hipLaunchKernel(k, dim3(grid / wpb), dim3(64 * wpb), args, 0, st);
 }
 
 int32_t band_blocks_per_cu(uint32_t sels, int32_t diags_per_lane, bool fp32)

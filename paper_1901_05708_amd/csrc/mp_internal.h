@@ -245,8 +245,10 @@ hipError_t launch_store_job(const Job &j, const RowBase4 &rb, Job *dst, int64_t 
                             hipStream_t st);
 hipError_t launch_prep(const Batch &b, uint32_t sels, hipStream_t st);
 hipError_t launch_plan(const Batch &b, hipStream_t st);
+// grid waves in blocks of wpb (1, or 4 where band_has_wave_blocks)
 hipError_t launch_sweep_band(const Batch &b, uint32_t sels, int32_t diags_per_lane, bool fp32,
-                             int32_t grid, hipStream_t st);
+                             int32_t grid, int32_t wpb, hipStream_t st);
+bool band_has_wave_blocks(uint32_t sels, int32_t diags_per_lane, bool fp32);
 hipError_t launch_sweep_simple(const Batch &b, hipStream_t st);
 hipError_t launch_finalize(const Batch &b, hipStream_t st);
 hipError_t launch_fallback(const Batch &b, hipStream_t st);
