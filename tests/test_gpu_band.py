@@ -269,6 +269,30 @@ def test_band_long_windows_runs_offset(mp):
                       atol_for(kind, m), rows=rows, label=f"long-offset-{kind}")
 
 
+@pytest.mark.parametrize("kind", ["aamp", "acamp"])
+def test_long_windows_many_runs(mp, kind):
+    """m = 2048 on a pattern of period 97 repeated under strong noise: every
+    multiple of the period is a near-tie, so neighbouring rows change winner
+    diagonal more often than on a plain series (Euclidean: about 20 runs
+    per 300 rows, more than the 16 anchor blocks per block of rows, so some
+    anchor blocks take two runs; z-normalized: one long run). Sampled rows
+    and a contiguous stretch of rows against the oracle."""
+    m, n = 2048, 9000
+    rng = np.random.default_rng(2049 + (kind == "acamp"))
+    T = np.tile(rng.standard_normal(97), n // 97 + 1)[:n] + 0.7 * rng.standard_normal(n)
+    excl = W.excl_default(m)
+    N = n - m + 1
+    rows = np.unique(np.concatenate([W.sample_rows(N, 96, 13), np.arange(3000, 3300)]))
+    _note(f"long windows many runs {kind}: n={n} m={m}")
+    P, I = _call(mp, kind, T, m, excl=excl, R=8 * m)
+    d = I[3000:3300] - np.arange(3000, 3300)
+    runs = 1 + np.count_nonzero(d[1:] != d[:-1])
+    _note(f"runs over 300 rows: {runs}")
+    Pr, Ir, Qr = oracle.profile(T, m, kind, excl=excl, rows=rows)
+    check_profile(T, m, kind, 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, 1e-9,
+                  atol_for(kind, m, "fp64", 8 * m), rows=rows, label=f"long-many-runs-{kind}")
+
+
 # ---- p-norms with other p (1 < p <= 6): a band kernel of their own ----
 
 @pytest.mark.parametrize("p", [1.5, 2.5, 4.7, 6.0])
