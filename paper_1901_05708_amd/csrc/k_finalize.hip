@@ -208,8 +208,8 @@ __device__ __forceinline__ void finalize_block(const Series &s, const Fallback &
 // the pair that enters (i + m - 1, j + m - 1) and subtracting the one that
 // leaves (i - 1, j - 1). A block of 256 rows splits into runs of consecutive
 // rows with a common winner diagonal; each run's first pair is summed over
-// its m terms by a block of its own, and a segmented prefix sum carries it
-// along the run.
+// its m terms by one of LONG_ANCHOR_SPLIT blocks set aside for the block of
+// rows, and a segmented prefix sum carries it along the run.
 // All of it is double-double (dd.h), so the running sums lose about 2^-104 of
 // their largest partial sum to cancellation instead of 2^-53. The quantities:
 //   AAMP, p-norm: the sum of (a - b)^2 or |a - b|^p (the terms rounded as in
@@ -237,7 +237,6 @@ struct FinLongLds {
     DD buf[FIN_BLOCK];
     long long diag[FIN_BLOCK];
     int ibuf[FIN_BLOCK];
-    int heads[FIN_BLOCK];
     double cb[FIN_BLOCK];
 };
 
@@ -308,7 +307,8 @@ __device__ __forceinline__ int long_runs(bool need, long long dg, FinLongLds &L,
 // another by the block of their rows:
 //  1. (k_finalize) decode the block's winners, find its runs and record them
 //     (lcount, lhead);
-//  2. (k_long_anchors) a block per run sums the run's first pair;
+//  2. (k_long_anchors) LONG_ANCHOR_SPLIT blocks per block of rows sum its
+//     runs' first pairs (run k in block k mod LONG_ANCHOR_SPLIT);
 //  3. (k_long_finish) each block slides the anchors along its runs and
 //     finishes its rows.
 template <int KIND, int PC>
