@@ -166,7 +166,7 @@ int mp_acamp_fcmp(const double *T, int64_t n, int32_t m, int32_t excl, int32_t R
  * allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc. It calls no hipMalloc, hipFree or other
  * allocating routine. Every array the pipeline needs lives in one static
- * device array of 48 MiB per GPU, held from the library's load until the
+ * device array of 56 MiB per GPU, held from the library's load until the
  * process ends; its address is looked up on the first call on each device.
  *
  * Arguments, layout and results are those of the single-series entry points,
