@@ -162,7 +162,7 @@ def test_ecg_2m(mp, kind):
     for prec in ("fp64", "fp32"):
         _note(f"ecg {kind} {prec}")
         P, I = _gpu(mp, kind, T, m, precision=prec)
-        _against_ref(f"ecg_{kind}", T, m, kind, 2.0, P, I, prec, f"ecg-{kind}-{prec}", 1024)
+        _against_ref(f"ecg_{kind}", T, m, kind, 2.0, P, I, prec, f"ecg-{kind}-{prec}", 4096)
         out[prec] = P
     _fp32_every_row(out["fp32"], out["fp64"], kind, f"ecg-{kind}")
 
@@ -179,7 +179,7 @@ def test_uniform_long_windows(mp, m, kind):
         _note(f"uniform n=2^18 m={m} {kind} {prec}")
         P, I = _gpu(mp, kind, T, m, precision=prec)
         _against_ref(f"uniform_m{m}_{kind}", T, m, kind, 2.0, P, I, prec,
-                     f"uniform-m{m}-{kind}-{prec}", 64)
+                     f"uniform-m{m}-{kind}-{prec}", 256 if m == 16384 else 64)
         out[prec] = P
     _fp32_every_row(out["fp32"], out["fp64"], kind, f"uniform-m{m}-{kind}")
 
