@@ -703,9 +703,12 @@ __device__ __forceinline__ void band_item(const Series &s, const int64_t k_lo, c
 // ring fields (16 KB of LDS per wave), so 12 waves do not fit a CU's 160 KB;
 // asking for 3 was 55 % slower. It, the mixed and the generic-p kernels keep
 // the default. FP32 with 8 diagonals per lane fits 4 waves without spills.
-template <uint32_t SELS, int KD, typename F>
+// Blocks of four waves serve only grids capped at one or two waves per SIMD:
+// asking for 4 there held the FP32 kernels to 128 registers and spilled 33-41.
+template <uint32_t SELS, int KD, typename F, int WPB>
 constexpr int waves_target()
 {
+    if (WPB == 4) return 2;
     if (KD != 8 || (SELS & SEL_LONG)) return 1;
     if (sizeof(F) == 4) return 4;
     return (SELS == SEL_AAMP || SELS == SEL_P1 || SELS == SEL_P3) ? 3 : 1;
@@ -720,7 +723,7 @@ constexpr int waves_target()
 // and none on another).
 template <uint32_t SELS, int KD, typename F, bool COUNT, int WPB>
 __global__ void __launch_bounds__(64 * WPB)
-    __attribute__((amdgpu_waves_per_eu(waves_target<SELS, KD, F>()))) k_sweep_band(Batch b)
+    __attribute__((amdgpu_waves_per_eu(waves_target<SELS, KD, F, WPB>()))) k_sweep_band(Batch b)
 {
     constexpr int RING = 64 * KD;
     constexpr int NF = (SELS & SEL_ACAMP) ? 3 : 2;
@@ -735,7 +738,7 @@ __global__ void __launch_bounds__(64 * WPB)
     F *rowop = rowbuf + NRB * 64;
     double *stage = lds;
 
-    constexpr bool RL = waves_target<SELS, KD, F>() != 3;
+    constexpr bool RL = waves_target<SELS, KD, F, WPB>() != 3;
     cint64 *row_base = as_const(b.row_base);
     cint64 *band_start = as_const(b.band_start);
     const int64_t total = row_base[b.njobs];   // band-row positions of the launch

@@ -205,27 +205,30 @@ def test_band_long_windows_pnorm_generic_fp32(mp):
 
 
 @pytest.mark.parametrize("wps", [1, 2])
-@pytest.mark.parametrize("kind,prec", [("aamp", "fp64"), ("acamp", "fp64"), ("acamp", "fp32")])
-def test_band_long_windows_long_refresh(mp, monkeypatch, kind, prec, wps):
+@pytest.mark.parametrize("kind,p,prec", [("aamp", 2.0, "fp64"), ("acamp", 2.0, "fp64"),
+                                         ("acamp", 2.0, "fp32"), ("pnorm", 1.0, "fp32")])
+def test_band_long_windows_long_refresh(mp, monkeypatch, kind, p, prec, wps):
     """m = 2048 over 20000 samples with the longest refresh interval the
-    autotuner allows (16 m) and grids capped at one and two waves per SIMD
-    (the sweep then runs in blocks of four waves): many long items, one exact
-    restart each. Checked on sampled rows."""
+    autotuner allows (16 m; m for the p = 1 sums in single precision) and
+    grids capped at one and two waves per SIMD (the sweep then runs in blocks
+    of four waves): many long items, one exact restart each. Checked on
+    sampled rows."""
     monkeypatch.setenv("MP_WPS", str(wps))
-    m, R = 2048, 16 * 2048
+    m = 2048
+    R = m if kind == "pnorm" else 16 * m
     T, _, _ = W.rw128k(n=20000, m=m, nruns=0, nmotifs=2, seed=31)
     excl = W.excl_default(m)
     N = len(T) - m + 1
     rows = W.sample_rows(N, 192, 32)
-    _note(f"long-refresh {kind} {prec}: n={len(T)} m={m} R={R} wps={wps}")
-    P, I = _call(mp, kind, T, m, excl=excl, R=R, precision=prec)
-    Pr, Ir, Qr = oracle.profile(T, m, kind, excl=excl, rows=rows)
+    _note(f"long-refresh {kind} p={p} {prec}: n={len(T)} m={m} R={R} wps={wps}")
+    P, I = _call(mp, kind, T, m, p=p, excl=excl, R=R, precision=prec)
+    Pr, Ir, Qr = oracle.profile(T, m, kind, p=p, excl=excl, rows=rows)
     if prec == "fp64":
         rtol, atol = 1e-9, atol_for(kind, m, "fp64", R)
     else:
-        rtol, atol = 1e-4, 1e-6
-    check_profile(T, m, kind, 2.0, excl, P[rows], I[rows], Pr, Ir, Qr, rtol, atol, rows=rows,
-                  label=f"long-refresh-{kind}-{prec}-wps{wps}")
+        rtol, atol = 1e-4, (1e-6 if kind == "acamp" else 0.0)
+    check_profile(T, m, kind, p, excl, P[rows], I[rows], Pr, Ir, Qr, rtol, atol, rows=rows,
+                  label=f"long-refresh-{kind}{p:g}-{prec}-wps{wps}")
 
 
 def test_band_long_windows_runs_offset(mp):
