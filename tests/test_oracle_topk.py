@@ -9,10 +9,10 @@ def test_hand_worked_motifs():
     P = np.array([5.0, 1.0, 4.0, 3.0, 1.0, 6.0, np.inf, 2.0, 2.0, 7.0])
     I = np.array([3, 4, 8, 0, 1, 9, -1, 2, 2, 5])
     i, j, d = topk(P, I, 10, 2, "motifs")
-    # round 1: min P = 1.0 at 1 and 4 -> 1 (smallest index), partner 4; excluded
-    #          0..2 and 3..5
-    # round 2: left 7, 8, 9 (6 is inf): min 2.0 at 7, partner 2; excluded 6..8
-    # round 3: left 9: P = 7, partner 5
+    # pick 1: min P = 1.0 at 1 and 4 -> 1 (smallest index), partner 4; excluded
+    #         0..2 and 3..5
+    # pick 2: left 7, 8, 9 (6 is inf): min 2.0 at 7, partner 2; excluded 6..8
+    # pick 3: left 9: P = 7, partner 5
     assert i.tolist() == [1, 7, 9]
     assert j.tolist() == [4, 2, 5]
     assert d.tolist() == [1.0, 2.0, 7.0]
