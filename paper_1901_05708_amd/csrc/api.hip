@@ -954,10 +954,12 @@ int record(hipEvent_t e, hipStream_t s)
 // on stream ls. Grids of one wave per SIMD can run either at full speed or
 // about 1.4 times slower from one launch to the next (the same grid measured
 // 9.2 and 13.4 ms on long windows: on some launches the hardware puts two of
-// the one-wave blocks on one SIMD and none on another), so a candidate counts
-// as fast only if both of its runs are; its faster run alone would let such a
-// grid win on a lucky trial and then run slow. A candidate whose first run already takes 1.5 times the
-// best time so far (best >= 0) is not run again: its first time is reported.
+// the one-wave blocks on one SIMD and none on another; capped grids now run
+// in blocks of four waves where the kernel has such an instance), so a
+// candidate counts as fast only if both of its runs are; its faster run alone
+// would let such a grid win on a lucky trial and then run slow. A candidate
+// whose first run already takes 1.5 times the best time so far (best >= 0) is
+// not run again: its first time is reported.
 int time_candidate(const std::vector<Spec> &specs, int32_t precision, const Tuning &tu,
                    Workspace &w, hipStream_t ls, hipEvent_t e0, hipEvent_t e1, float best,
                    float *ms)
